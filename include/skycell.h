@@ -1,0 +1,172 @@
+/*
+ * skycell.h -- C ABI of the MI355X (gfx950) exact-skyline library.
+ *
+ * The library computes the skyline of n points in d attributes (SkyCell paper,
+ * Section III, Definitions 1-2): point p dominates q iff p[k] <= q[k] in every
+ * dimension and p[l] < q[l] in at least one; the skyline is the set of points no
+ * other point dominates.  Smaller is better.  The result is exact and unique; it
+ * is returned as ascending int32 indices, every exact copy of a skyline point
+ * included (copies never dominate each other).
+ *
+ * Method (Section V, Algorithm 1, single grid layer): points are mapped to a
+ * regular grid of g cells per dimension (Equation 1); cells dominated by a
+ * non-empty cell (Definition 3: smaller column in every dimension) are pruned,
+ * since they cannot hold skyline points; each remaining point is then checked
+ * for point domination against the points of the non-empty cells in its lower
+ * cone (cells whose columns are <= its own in every dimension), which is the
+ * only place a dominator can sit.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller.  Work is enqueued
+ *     on `stream` (a hipStream_t passed as void*, NULL = default stream) and runs
+ *     asynchronously: the caller keeps inputs alive and reads outputs only after
+ *     the stream has passed this call.
+ *   - `points` is structure-of-arrays: attribute k of point i is points[k*n + i].
+ *   - `out_idx` needs capacity n; `out_idx[0 .. *out_count)` receives the skyline
+ *     indices in ascending order.  `*out_count` is written on the device; a
+ *     negative value there is a device-detected error (SKYCELL_E_NAN).
+ *   - The return value is SKYCELL_OK or a negative code, decided on the host.
+ *     All argument checks happen before any HIP call, so they also work on a
+ *     machine without a GPU.  skycell_last_error() describes the last failure
+ *     of the calling thread.  No C++ exception crosses this interface.
+ *   - The result never depends on grid_res, on the autotuner or on tuning.
+ */
+#ifndef SKYCELL_H
+#define SKYCELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SKYCELL_OK = 0,
+    SKYCELL_E_INVAL = -1, /* null pointer, n < 0, n >= 2^31, d outside [1, 16], bad enum  */
+    SKYCELL_E_RANGE = -2, /* grid of g^d cells exceeds SKYCELL_MAX_CELLS, bad value_bits   */
+    SKYCELL_E_NOMEM = -3, /* device allocation failed, or workspace smaller than required  */
+    SKYCELL_E_HIP = -4,   /* a HIP runtime call or kernel launch failed                    */
+    SKYCELL_E_NODEV = -5, /* no usable GPU                                                 */
+    SKYCELL_E_NAN = -6    /* written to *out_count when the input holds a NaN              */
+};
+
+#define SKYCELL_MAX_D 16
+#define SKYCELL_MAX_CELLS (1u << 26)
+
+#define SKYCELL_DTYPE_F32 0
+#define SKYCELL_DTYPE_U16 1
+
+/* Number of uint64 counters written by the *_stats variants (device memory). */
+#define SKYCELL_NUM_STATS 8
+/* Indices into the stats array.                                               */
+#define SKYCELL_STAT_NONEMPTY_CELLS 0  /* cells holding at least one point           */
+#define SKYCELL_STAT_SURVIVING_CELLS 1 /* non-empty cells not dominated (Def. 3)     */
+#define SKYCELL_STAT_SURVIVOR_POINTS 2 /* points in surviving cells                  */
+#define SKYCELL_STAT_ITEMS 3           /* refine work items (groups of query points) */
+#define SKYCELL_STAT_CELL_VISITS 4     /* lower-cone cells visited by the refine     */
+#define SKYCELL_STAT_PAIR_TESTS 5      /* candidate x query point domination tests   */
+#define SKYCELL_STAT_SKYLINE 6         /* number of skyline points                   */
+#define SKYCELL_STAT_GRID_RES 7        /* cells per dimension used                   */
+
+/*
+ * Exact skyline of binary32 points (Definitions 1-2).
+ *   points    device, SoA [d][n] binary32.  Any finite value or +-inf is accepted
+ *             (values outside [0, 1) land in the border cells, Equation 1 with a
+ *             clamp); -0.0 equals +0.0; a NaN makes *out_count = SKYCELL_E_NAN.
+ *   n         number of points, 0 <= n < 2^31.  n = 0 writes *out_count = 0.
+ *   d         number of attributes, 1 <= d <= SKYCELL_MAX_D.
+ *   grid_res  cells per dimension g >= 1 (the paper uses g = 2^rho, Section III);
+ *             0 lets the library choose (skycell_choose_grid).  g^d must not
+ *             exceed SKYCELL_MAX_CELLS.
+ *   out_idx   device int32 [n], written.      out_count  device int32 [1], written.
+ *   stream    hipStream_t or NULL.
+ * The library keeps a workspace per (device, stream), grown on demand with
+ * hipMalloc; use skycell_compute_ws to supply it instead.
+ */
+int skycell_compute(const float *points, int64_t n, int32_t d, int32_t grid_res,
+                    int32_t *out_idx, int32_t *out_count, void *stream);
+
+/*
+ * Same for unsigned 16-bit attributes (integer-valued data with many ties).
+ *   value_bits  values are expected below 2^value_bits (1..16); the column of v
+ *               is floor(v * g / 2^value_bits), clamped to g-1.  Larger values
+ *               stay exact but land in the top cell.
+ */
+int skycell_compute_u16(const uint16_t *points, int64_t n, int32_t d, int32_t grid_res,
+                        int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *stream);
+
+/*
+ * Workspace size in bytes for skycell_compute_ws with these arguments.
+ *   dtype  SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16.  grid_res 0 = autotuned.
+ */
+int skycell_workspace_bytes(int64_t n, int32_t d, int32_t grid_res, int32_t dtype,
+                            size_t *bytes);
+
+/*
+ * Exact skyline with a caller-supplied workspace: no allocation happens inside.
+ *   points      device SoA [d][n], binary32 (dtype F32) or uint16 (dtype U16).
+ *   value_bits  used for U16 only (see skycell_compute_u16).
+ *   workspace   device memory of at least skycell_workspace_bytes(...) bytes,
+ *               256-byte aligned; its contents are scratch for this call only.
+ *               Two calls that overlap in time must not share a workspace.
+ *   stats       NULL, or device uint64 [SKYCELL_NUM_STATS] receiving the
+ *               counters listed above (this adds a few atomics per wave).
+ */
+int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d,
+                       int32_t grid_res, int32_t value_bits, int32_t *out_idx,
+                       int32_t *out_count, void *workspace, size_t ws_bytes,
+                       uint64_t *stats, void *stream);
+
+/*
+ * Grid resolution the library uses when grid_res = 0: the autotuner's entry for
+ * (d, n, dtype) if a tuning table is loaded, else a rule that keeps about one
+ * to two cells per point under the cell budget (Section VI: rho <= log(n)/d).
+ */
+int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res);
+
+/*
+ * Load an autotuner table (text, one "d log2n dtype g" line per entry).  NULL
+ * clears it.  Applies to all later calls in the process.
+ */
+int skycell_load_tuning(const char *path);
+
+/*
+ * Byte offsets of the workspace's sub-buffers for (n, d, grid_res) (grid_res 0 =
+ * autotuned), for tests and tools that inspect intermediate results of a
+ * skycell_compute_ws call.  offsets[0..count) receives, in this order:
+ *   0 cell_of  uint32 [n]        cell of each input point (mixed radix, dim 0 fastest)
+ *   1 cnt      uint32 [cells]    histogram (consumed by the scatter)
+ *   2 lc       uint8  [cells]    lower closure of the occupancy
+ *   3 info     uint32 [cells]    bit 31: surviving non-empty cell; bits 0..d-1: cone mask
+ *   4 offs     uint32 [cells+1]  first sorted position of each surviving cell
+ *   5 keys     uint32 [n*d]      sorted surviving points as order-preserving keys
+ *   6 sidx     int32  [n]        original index of each sorted point
+ *   7 items, 8 flag, 9 block sums, 10 counters, 11 total size.
+ * count must be >= 12.  Returns SKYCELL_OK or an argument error.
+ */
+int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dtype,
+                             size_t *offsets, int32_t count);
+
+/*
+ * Phase timing.  After skycell_profile_enable(1), every later call on the
+ * calling thread records hipEvents on its stream between the phases of the
+ * path.  skycell_profile_read waits for the last recorded event and writes the
+ * milliseconds of the last profiled call, phase by phase, in this order:
+ *   0 init + quantise/histogram (Equation 1)   1 cell prune (Definition 3)
+ *   2 cell scan (offsets, work items)          3 scatter of surviving points
+ *   4 refine (lower-cone point domination)     5 ordered output
+ * count must be >= SKYCELL_NUM_PHASES.  Disabling frees the events.
+ */
+#define SKYCELL_NUM_PHASES 6
+int skycell_profile_enable(int32_t on);
+int skycell_profile_read(float *ms, int32_t count);
+
+/* Text for the last nonzero return of the calling thread ("" if none). */
+const char *skycell_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKYCELL_H */

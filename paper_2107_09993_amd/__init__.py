@@ -1,0 +1,198 @@
+"""MI355X (gfx950) exact skyline following SkyCell (arXiv 2107.09993).
+
+Thin Python binding over the C ABI of ``libskycell.so`` (declared in
+``include/skycell.h``).  It only marshals arguments: PyTorch provides device
+memory and the stream, every step of the skyline runs in the library's HIP
+kernels.  There is no CPU fallback; if the library is missing, calls raise.
+
+    import torch, paper_2107_09993_amd as sky
+    x = torch.rand(1_000_000, 8, device="cuda")
+    idx = sky.compute(x)          # ascending int32 indices of the skyline points
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libskycell.so")
+
+OK = 0
+E_INVAL = -1
+E_RANGE = -2
+E_NOMEM = -3
+E_HIP = -4
+E_NODEV = -5
+E_NAN = -6
+MAX_D = 16
+MAX_CELLS = 1 << 26
+DTYPE_F32 = 0
+DTYPE_U16 = 1
+NUM_STATS = 8
+STAT_NAMES = ("nonempty_cells", "surviving_cells", "survivor_points", "items", "cell_visits",
+              "pair_tests", "skyline", "grid_res")
+
+_lib = None
+
+
+class SkycellError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("skycell error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """The loaded ctypes library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libskycell.so is not built (run: python -m paper_2107_09993_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, p, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+    L.skycell_compute.argtypes = [p, i64, i32, i32, p, p, p]
+    L.skycell_compute_u16.argtypes = [p, i64, i32, i32, i32, p, p, p]
+    L.skycell_workspace_bytes.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz)]
+    L.skycell_compute_ws.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, sz, p, p]
+    L.skycell_choose_grid.argtypes = [i64, i32, i32, ctypes.POINTER(i32)]
+    L.skycell_load_tuning.argtypes = [ctypes.c_char_p]
+    L.skycell_workspace_layout.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz), i32]
+    L.skycell_profile_enable.argtypes = [i32]
+    L.skycell_profile_read.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
+    L.skycell_last_error.argtypes = []
+    L.skycell_last_error.restype = ctypes.c_char_p
+    for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
+                 "skycell_compute_ws", "skycell_choose_grid", "skycell_load_tuning",
+                 "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        raise SkycellError(rc, lib().skycell_last_error().decode())
+
+
+def last_error():
+    return lib().skycell_last_error().decode()
+
+
+def workspace_bytes(n, d, grid_res=0, dtype=DTYPE_F32):
+    out = ctypes.c_size_t(0)
+    _check(lib().skycell_workspace_bytes(int(n), int(d), int(grid_res), int(dtype), ctypes.byref(out)))
+    return out.value
+
+
+def choose_grid(n, d, dtype=DTYPE_F32):
+    g = ctypes.c_int32(0)
+    _check(lib().skycell_choose_grid(int(n), int(d), int(dtype), ctypes.byref(g)))
+    return g.value
+
+
+NUM_PHASES = 6
+PHASE_NAMES = ("quantize_hist", "cell_prune", "cell_scan", "scatter", "refine", "output")
+
+
+def profile_enable(on=True):
+    _check(lib().skycell_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """Milliseconds per phase of the last profiled call on this thread (waits for it)."""
+    ms = (ctypes.c_float * NUM_PHASES)()
+    _check(lib().skycell_profile_read(ms, NUM_PHASES))
+    return dict(zip(PHASE_NAMES, (float(v) for v in ms)))
+
+
+def workspace_layout(n, d, grid_res=0, dtype=DTYPE_F32):
+    offs = (ctypes.c_size_t * 12)()
+    _check(lib().skycell_workspace_layout(int(n), int(d), int(grid_res), int(dtype), offs, 12))
+    return list(offs)
+
+
+def load_tuning(path):
+    _check(lib().skycell_load_tuning(path.encode() if path else None))
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return DTYPE_F32
+    if t.dtype == torch.uint16:
+        return DTYPE_U16
+    raise TypeError("points must be float32 or uint16, got %s" % t.dtype)
+
+
+def to_soa(points):
+    """[n, d] tensor -> contiguous [d, n] (structure of arrays) on the same device."""
+    return points.t().contiguous()
+
+
+class Skyline:
+    """Reusable buffers for repeated skyline calls on one shape (device memory from torch).
+
+    ``run(points_soa)`` enqueues the whole path on the current stream and returns the
+    device tensors (out_idx, out_count) without synchronising.
+    """
+
+    def __init__(self, n, d, dtype="f32", grid_res=0, value_bits=10, device="cuda", stats=False):
+        import torch
+        self.n, self.d = int(n), int(d)
+        self.dtype = DTYPE_F32 if dtype in ("f32", DTYPE_F32) else DTYPE_U16
+        self.value_bits = int(value_bits) if self.dtype == DTYPE_U16 else 16
+        self.grid_res = grid_res if grid_res else choose_grid(self.n, self.d, self.dtype)
+        self.device = torch.device(device)
+        self.ws_bytes = workspace_bytes(self.n, self.d, self.grid_res, self.dtype)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.out_idx = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        self.out_count = torch.empty(1, dtype=torch.int32, device=self.device)
+        self.stats = torch.zeros(NUM_STATS, dtype=torch.int64, device=self.device) if stats else None
+
+    def run(self, points_soa, stream=None):
+        import torch
+        if points_soa.device != self.device or not points_soa.is_contiguous():
+            raise ValueError("points must be a contiguous [d, n] tensor on %s" % self.device)
+        if tuple(points_soa.shape) != (self.d, self.n):
+            raise ValueError("points must have shape (%d, %d), got %s" % (self.d, self.n, tuple(points_soa.shape)))
+        if _dtype_code(points_soa) != self.dtype:
+            raise TypeError("dtype mismatch")
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib().skycell_compute_ws(
+            ctypes.c_void_p(points_soa.data_ptr()), self.dtype, self.n, self.d, self.grid_res,
+            self.value_bits, ctypes.c_void_p(self.out_idx.data_ptr()),
+            ctypes.c_void_p(self.out_count.data_ptr()), ctypes.c_void_p(self.workspace.data_ptr()),
+            self.ws_bytes, ctypes.c_void_p(self.stats.data_ptr()) if self.stats is not None else None,
+            ctypes.c_void_p(st))
+        _check(rc)
+        return self.out_idx, self.out_count
+
+    def result(self):
+        """Synchronise on the count and return the skyline indices (int32 tensor)."""
+        c = int(self.out_count.item())
+        if c < 0:
+            raise SkycellError(c, "device reported %s" % ("NaN in input" if c == E_NAN else "error"))
+        return self.out_idx[:c]
+
+    def stats_dict(self):
+        if self.stats is None:
+            return {}
+        return dict(zip(STAT_NAMES, (int(v) for v in self.stats.cpu().tolist())))
+
+
+def compute(points, grid_res=0, layout="nd", value_bits=10, return_stats=False):
+    """Exact skyline of a CUDA tensor of points (float32 or uint16).
+
+    layout "nd": points is [n, d] (transposed to SoA first); "dn": points is [d, n].
+    Returns ascending int32 indices (a CUDA tensor); with return_stats also a dict
+    of the library's counters.
+    """
+    if not points.is_cuda:
+        raise ValueError("points must be a CUDA (HIP) tensor")
+    soa = to_soa(points) if layout == "nd" else points.contiguous()
+    d, n = soa.shape
+    sk = Skyline(n, d, dtype=_dtype_code(soa), grid_res=grid_res, value_bits=value_bits,
+                 device=soa.device, stats=return_stats)
+    sk.run(soa)
+    out = sk.result().clone()
+    if return_stats:
+        return out, sk.stats_dict()
+    return out

@@ -1,0 +1,306 @@
+// Grid phase of the skyline path (SkyCell paper, Section III grid structure and
+// Section V, Algorithm 1 line 1):
+//   K1  quantise every point to its cell (Equation 1) and build the occupancy
+//       histogram;
+//   K3  lower closure of the occupancy by d prefix-OR passes, then per cell the
+//       "dominated" test of Definition 3 and the lower-neighbour mask used by the
+//       refine's cone walk;
+//   K2  exclusive scan of surviving-cell counts: counting-sort offsets and refine
+//       work items;
+//   K4  scatter of surviving points, grouped by cell, as order-preserving keys.
+#include "common.h"
+#include "scan.h"
+#include "../../include/skycell.h"
+
+namespace skycell {
+
+constexpr int kThreads = 256;
+
+static inline dim3 grid_for(uint64_t count, int per_block = kThreads)
+{
+    uint64_t b = (count + per_block - 1) / per_block;
+    if (b == 0) b = 1;
+    return dim3((unsigned)b);
+}
+
+// ------------------------------------------------------------------ init
+__global__ __launch_bounds__(kThreads) void k_init(uint32_t *cnt, uint32_t cells, uint32_t *ctr,
+                                                   uint64_t *stats, int32_t g)
+{
+    const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t stride = gridDim.x * kThreads;
+    for (uint32_t i = gid; i < cells; i += stride) cnt[i] = 0u;
+    if (gid < kCtrCount) ctr[gid] = 0u;
+    if (stats != nullptr && gid < SKYCELL_NUM_STATS) stats[gid] = gid == SKYCELL_STAT_GRID_RES ? (uint64_t)g : 0ull;
+}
+
+hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats, hipStream_t st)
+{
+    uint32_t blocks = (gd.cells + kThreads * 8 - 1) / (kThreads * 8);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kThreads), 0, st, ws.cnt, gd.cells, ws.ctr, stats, gd.g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ K1
+// Column of a binary32 value: floor of the binary32 product x*g (round to
+// nearest), clamped to [0, g-1].  Non-decreasing in x, which is all that cell
+// pruning needs to stay exact.
+__device__ __forceinline__ uint32_t column_f32(float v, float gf, uint32_t g, bool &nan)
+{
+    if (v != v) {
+        nan = true;
+        return 0u;
+    }
+    const float f = floorf(__fmul_rn(v, gf));
+    if (!(f >= 0.0f)) return 0u;
+    if (f >= gf) return g - 1u;
+    return (uint32_t)f;
+}
+
+__device__ __forceinline__ uint32_t column_u16(uint16_t v, uint32_t g, int bits)
+{
+    const uint64_t c = ((uint64_t)v * g) >> bits;
+    return c > g - 1u ? g - 1u : (uint32_t)c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict__ pts, uint32_t n,
+                                                            GridDesc gd, int value_bits,
+                                                            uint32_t *__restrict__ cell_of,
+                                                            uint32_t *__restrict__ cnt,
+                                                            uint32_t *__restrict__ ctr)
+{
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float gf = (float)gd.g;
+    uint32_t cell = 0u;
+    bool nan = false;
+    for (int k = 0; k < gd.d; ++k) {
+        const T v = pts[(size_t)k * n + i];
+        uint32_t c;
+        if constexpr (sizeof(T) == 4)
+            c = column_f32(v, gf, (uint32_t)gd.g, nan);
+        else
+            c = column_u16(v, (uint32_t)gd.g, value_bits);
+        cell += c * gd.stride[k];
+    }
+    cell_of[i] = cell;
+    atomicAdd(&cnt[cell], 1u);
+    if (nan) atomicOr(&ctr[kCtrErr], 1u);
+}
+
+hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const GridDesc &gd,
+                                int value_bits, const Workspace &ws, hipStream_t st)
+{
+    if (dtype == SKYCELL_DTYPE_F32)
+        hipLaunchKernelGGL(k_quantize_hist<float>, grid_for(n), dim3(kThreads), 0, st,
+                           (const float *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.cnt, ws.ctr);
+    else
+        hipLaunchKernelGGL(k_quantize_hist<uint16_t>, grid_for(n), dim3(kThreads), 0, st,
+                           (const uint16_t *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.cnt,
+                           ws.ctr);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ K3
+// lc[x] = 1 iff some non-empty cell y has y <= x in every dimension.  Built as
+// the occupancy followed by an inclusive prefix-OR along each dimension.
+__global__ __launch_bounds__(kThreads) void k_lc_init(const uint32_t *__restrict__ cnt,
+                                                      uint8_t *__restrict__ lc, uint32_t cells)
+{
+    const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
+    if (x < cells) lc[x] = cnt[x] != 0u ? 1 : 0;
+}
+
+// One thread per line of cells that differ only in dimension k.
+__global__ __launch_bounds__(kThreads) void k_lc_prefix(uint8_t *__restrict__ lc, uint32_t lines,
+                                                        uint32_t stride, uint32_t g)
+{
+    const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= lines) return;
+    const uint32_t lo = t % stride, hi = t / stride;
+    uint32_t x = hi * stride * g + lo;
+    uint8_t v = 0;
+    for (uint32_t j = 0; j < g; ++j, x += stride) {
+        v |= lc[x];
+        lc[x] = v;
+    }
+}
+
+// Per cell: the surviving flag and the lower-neighbour mask.
+//   dominated(x)  iff  every column of x is >= 1 and lc[x - (1,...,1)] = 1,
+//   i.e. a non-empty cell has a smaller column in every dimension (Definition 3).
+//   nbr bit k     iff  column k of x is >= 1 and lc[x - e_k] = 1, i.e. the cone
+//                      below x - e_k still holds a non-empty cell.
+__global__ __launch_bounds__(kThreads) void k_cell_info(GridDesc gd, const uint32_t *__restrict__ cnt,
+                                                        const uint8_t *__restrict__ lc,
+                                                        uint32_t *__restrict__ info,
+                                                        uint64_t *__restrict__ stats)
+{
+    const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
+    bool occ = false, surv = false;
+    if (x < gd.cells) {
+        uint32_t rem = x, nbr = 0u;
+        bool all_pos = true;
+        for (int k = 0; k < gd.d; ++k) {
+            const uint32_t c = rem % (uint32_t)gd.g;
+            rem /= (uint32_t)gd.g;
+            if (c == 0u) {
+                all_pos = false;
+            } else if (lc[x - gd.stride[k]]) {
+                nbr |= 1u << k;
+            }
+        }
+        occ = cnt[x] != 0u;
+        surv = occ && !(all_pos && lc[x - gd.diag]);
+        info[x] = nbr | (surv ? kOccBit : 0u);
+    }
+    if (stats != nullptr) {
+        const uint64_t bo = __ballot(occ), bs = __ballot(surv);
+        if (__lane_id() == 0) {
+            if (bo) atomicAdd((unsigned long long *)&stats[SKYCELL_STAT_NONEMPTY_CELLS],
+                              (unsigned long long)__popcll(bo));
+            if (bs) atomicAdd((unsigned long long *)&stats[SKYCELL_STAT_SURVIVING_CELLS],
+                              (unsigned long long)__popcll(bs));
+        }
+    }
+}
+
+hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lc_init, grid_for(gd.cells), dim3(kThreads), 0, st, ws.cnt, ws.lc, gd.cells);
+    const uint32_t lines = gd.cells / (uint32_t)gd.g;
+    if (gd.g > 1) {
+        for (int k = 0; k < gd.d; ++k)
+            hipLaunchKernelGGL(k_lc_prefix, grid_for(lines), dim3(kThreads), 0, st, ws.lc, lines,
+                               gd.stride[k], (uint32_t)gd.g);
+    }
+    hipLaunchKernelGGL(k_cell_info, grid_for(gd.cells), dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
+                       ws.info, stats);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ K2
+// Scan value per cell: surviving points (low 32 bits) and refine work items
+// (high 32 bits); a cell with m surviving points gives ceil(m / M) items.
+struct CellLoader {
+    const uint32_t *info;
+    const uint32_t *cnt;
+    uint32_t per_item;
+    __device__ uint64_t operator()(uint64_t x) const
+    {
+        const uint32_t m = (info[x] & kOccBit) ? cnt[x] : 0u;
+        const uint32_t it = (m + per_item - 1u) / per_item;
+        return (uint64_t)m | ((uint64_t)it << 32);
+    }
+};
+
+// Item = (first sorted position, (point count << 26) | cell).
+struct CellEmitter {
+    uint32_t *offs;
+    uint2 *items;
+    uint32_t per_item;
+    __device__ void operator()(uint64_t x, uint64_t prefix, uint64_t v) const
+    {
+        const uint32_t start = (uint32_t)prefix;
+        offs[x] = start;
+        const uint32_t m = (uint32_t)v;
+        const uint32_t it = (uint32_t)(v >> 32);
+        const uint32_t ibase = (uint32_t)(prefix >> 32);
+        for (uint32_t t = 0; t < it; ++t) {
+            const uint32_t first = t * per_item;
+            const uint32_t c = (m - first) < per_item ? (m - first) : per_item;
+            items[ibase + t] = make_uint2(start + first, (c << 26) | (uint32_t)x);
+        }
+    }
+};
+
+__global__ void k_cell_scan_total(const uint64_t *block_sums, uint32_t nb, uint32_t cells,
+                                  uint32_t *offs, uint32_t *ctr, uint64_t *stats)
+{
+    const uint64_t tot = block_sums[nb];
+    offs[cells] = (uint32_t)tot;
+    ctr[kCtrSurvPts] = (uint32_t)tot;
+    ctr[kCtrItems] = (uint32_t)(tot >> 32);
+    if (stats != nullptr) {
+        stats[SKYCELL_STAT_SURVIVOR_POINTS] = (uint32_t)tot;
+        stats[SKYCELL_STAT_ITEMS] = tot >> 32;
+    }
+}
+
+hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st)
+{
+    const uint32_t m = (uint32_t)items_per_group(gd.d);
+    CellLoader ld{ws.info, ws.cnt, m};
+    CellEmitter em{ws.offs, ws.items, m};
+    hipError_t e = enqueue_scan<uint64_t>(ld, em, gd.cells, ws.block_sums, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_scan_total, dim3(1), dim3(1), 0, st, (const uint64_t *)ws.block_sums,
+                       scan_tiles(gd.cells), gd.cells, ws.offs, ws.ctr, stats);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ K4
+// Counting-sort scatter of the points of surviving cells.  The slot inside a
+// cell comes from an atomic cursor, so the order inside a cell is arbitrary;
+// the skyline does not depend on it.  Also clears the output flag of every point.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts, uint32_t n, int d,
+                                                      const uint32_t *__restrict__ cell_of,
+                                                      const uint32_t *__restrict__ info,
+                                                      const uint32_t *__restrict__ offs,
+                                                      uint32_t *__restrict__ cnt,
+                                                      uint32_t *__restrict__ keys,
+                                                      int32_t *__restrict__ sidx,
+                                                      uint8_t *__restrict__ flag)
+{
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = 0;
+    const uint32_t x = cell_of[i];
+    if (!(info[x] & kOccBit)) return;
+    const uint32_t pos = offs[x] + atomicSub(&cnt[x], 1u) - 1u;
+    uint32_t *dst = keys + (size_t)pos * d;
+    for (int k = 0; k < d; ++k) {
+        const T v = pts[(size_t)k * n + i];
+        if constexpr (sizeof(T) == 4)
+            dst[k] = f32_key(v);
+        else
+            dst[k] = (uint32_t)v;
+    }
+    sidx[pos] = (int32_t)i;
+}
+
+hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
+                          const Workspace &ws, hipStream_t st)
+{
+    if (dtype == SKYCELL_DTYPE_F32)
+        hipLaunchKernelGGL(k_scatter<float>, grid_for(n), dim3(kThreads), 0, st, (const float *)pts,
+                           (uint32_t)n, gd.d, ws.cell_of, ws.info, ws.offs, ws.cnt, ws.keys, ws.sidx,
+                           ws.flag);
+    else
+        hipLaunchKernelGGL(k_scatter<uint16_t>, grid_for(n), dim3(kThreads), 0, st,
+                           (const uint16_t *)pts, (uint32_t)n, gd.d, ws.cell_of, ws.info, ws.offs,
+                           ws.cnt, ws.keys, ws.sidx, ws.flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scan partials
+__global__ __launch_bounds__(kPartialThreads) void k_scan_partials(uint64_t *block_sums, uint32_t nb)
+{
+    __shared__ uint64_t s_w[kPartialThreads / kWave];
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += kPartialThreads) {
+        const uint32_t i = base + threadIdx.x;
+        const uint64_t v = i < nb ? block_sums[i] : 0ull;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan<uint64_t, kPartialThreads>(v, &tot, s_w);
+        if (i < nb) block_sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) block_sums[nb] = carry;
+}
+
+}  // namespace skycell

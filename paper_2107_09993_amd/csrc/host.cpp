@@ -1,0 +1,436 @@
+// C ABI of the skyline library: argument checks (before any HIP call), grid
+// choice, workspace layout and the launch sequence of the plain path.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/skycell.h"
+#include "common.h"
+#include "scan.h"
+
+namespace skycell {
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+static int ok()
+{
+    g_last_error.clear();
+    return SKYCELL_OK;
+}
+
+// ---------------------------------------------------------------- grid choice
+struct TuneEntry {
+    int d;
+    int log2n;
+    int dtype;
+    int g;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+// g^d with saturation above the cell budget.
+static uint64_t cells_of(int g, int d)
+{
+    uint64_t c = 1;
+    for (int k = 0; k < d; ++k) {
+        c *= (uint64_t)g;
+        if (c > (uint64_t)kMaxCells) return (uint64_t)kMaxCells + 1;
+    }
+    return c;
+}
+
+static int default_grid(int64_t n, int d)
+{
+    // About two cells per point (one point per finest cell is the paper's
+    // largest useful layer, Section VI), bounded below so tiny inputs still
+    // get a grid and above by 2^24 cells.
+    double target = 2.0 * (double)n;
+    if (target < 4096.0) target = 4096.0;
+    if (target > (double)(1u << 24)) target = (double)(1u << 24);
+    int g = 1;
+    while (cells_of(g + 1, d) <= (uint64_t)target) ++g;
+    return g;
+}
+
+static int choose_grid(int64_t n, int d, int dtype)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int best = -1, best_dist = 1 << 30;
+    const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
+    for (const TuneEntry &e : g_tune) {
+        if (e.d != d || e.dtype != dtype) continue;
+        const int dist = std::abs(e.log2n - l2);
+        if (dist < best_dist) {
+            best_dist = dist;
+            best = e.g;
+        }
+    }
+    if (best >= 1 && cells_of(best, d) <= kMaxCells) return best;
+    return default_grid(n, d);
+}
+
+static GridDesc make_grid(int d, int g)
+{
+    GridDesc gd;
+    memset(&gd, 0, sizeof(gd));
+    gd.d = d;
+    gd.g = g;
+    uint32_t s = 1, diag = 0;
+    for (int k = 0; k < d; ++k) {
+        gd.stride[k] = s;
+        diag += s;
+        s *= (uint32_t)g;
+    }
+    gd.cells = s;
+    gd.diag = diag;
+    int bits = 1;
+    while (((uint64_t)1 << bits) <= (uint64_t)(g - 1)) ++bits;
+    int logw = 0;
+    while ((1 << logw) < bits) ++logw;
+    gd.log_w = logw;
+    return gd;
+}
+
+// ---------------------------------------------------------------- workspace
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes > 0 ? bytes : 1);
+        return p;
+    };
+    const size_t nn = (size_t)n;
+    Workspace w;
+    w.cell_of = (uint32_t *)take(4 * nn);
+    w.cnt = (uint32_t *)take(4 * (size_t)cells);
+    w.lc = (uint8_t *)take((size_t)cells);
+    w.info = (uint32_t *)take(4 * (size_t)cells);
+    w.offs = (uint32_t *)take(4 * ((size_t)cells + 1));
+    w.keys = (uint32_t *)take(4 * nn * (size_t)d);
+    w.sidx = (int32_t *)take(4 * nn);
+    w.items = (uint2 *)take(8 * nn);
+    w.flag = (uint8_t *)take(nn);
+    const uint64_t tiles = std::max<uint64_t>(scan_tiles(cells), scan_tiles(nn));
+    w.block_sums = (uint64_t *)take(8 * (size_t)(tiles + 1));
+    w.ctr = (uint32_t *)take(4 * kCtrCount);
+    if (ws) *ws = w;
+    return off;
+}
+
+// ---------------------------------------------------------------- devices
+static std::mutex g_dev_mu;
+static std::map<int, int> g_num_cus;
+
+static int device_cus(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_num_cus.find(dev);
+    if (it != g_num_cus.end()) return it->second;
+    hipDeviceProp_t prop;
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    if (cus < 1) cus = 1;
+    g_num_cus[dev] = cus;
+    return cus;
+}
+
+struct CachedWs {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, CachedWs> g_ws_cache;
+
+// ---------------------------------------------------------------- validation
+static int validate(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
+                    int32_t value_bits, const int32_t *out_idx, const int32_t *out_count)
+{
+    if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16)
+        return fail(SKYCELL_E_INVAL, "dtype %d is not SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16", dtype);
+    if (n < 0) return fail(SKYCELL_E_INVAL, "n = %lld is negative", (long long)n);
+    if (n >= ((int64_t)1 << 31)) return fail(SKYCELL_E_INVAL, "n = %lld is not below 2^31", (long long)n);
+    if (d < 1 || d > SKYCELL_MAX_D)
+        return fail(SKYCELL_E_INVAL, "d = %d is outside [1, %d]", d, SKYCELL_MAX_D);
+    if (grid_res < 0) return fail(SKYCELL_E_INVAL, "grid_res = %d is negative", grid_res);
+    if (out_count == nullptr) return fail(SKYCELL_E_INVAL, "out_count is NULL");
+    if (n > 0 && points == nullptr) return fail(SKYCELL_E_INVAL, "points is NULL");
+    if (n > 0 && out_idx == nullptr) return fail(SKYCELL_E_INVAL, "out_idx is NULL");
+    if (dtype == SKYCELL_DTYPE_U16 && (value_bits < 1 || value_bits > 16))
+        return fail(SKYCELL_E_RANGE, "value_bits = %d is outside [1, 16]", value_bits);
+    return SKYCELL_OK;
+}
+
+static int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out)
+{
+    const int g = grid_res > 0 ? grid_res : choose_grid(n, d, dtype);
+    if (cells_of(g, d) > kMaxCells)
+        return fail(SKYCELL_E_RANGE, "grid of %d^%d cells exceeds the budget of %u cells", g, d,
+                    (unsigned)kMaxCells);
+    *g_out = g;
+    return SKYCELL_OK;
+}
+
+#define SKYCELL_HIP_CHECK(expr)                                                          \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(SKYCELL_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- phase timing
+struct Profiler {
+    bool on = false;
+    int device = -1;
+    hipEvent_t ev[SKYCELL_NUM_PHASES + 1] = {};
+    bool recorded = false;
+};
+static thread_local Profiler g_prof;
+
+static void prof_free()
+{
+    for (hipEvent_t &e : g_prof.ev)
+        if (e != nullptr) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    g_prof.recorded = false;
+}
+
+static int prof_mark(int i, hipStream_t st)
+{
+    if (!g_prof.on) return SKYCELL_OK;
+    int dev = 0;
+    SKYCELL_HIP_CHECK(hipGetDevice(&dev));
+    if (g_prof.device != dev) {
+        prof_free();
+        g_prof.device = dev;
+    }
+    if (g_prof.ev[i] == nullptr) SKYCELL_HIP_CHECK(hipEventCreate(&g_prof.ev[i]));
+    SKYCELL_HIP_CHECK(hipEventRecord(g_prof.ev[i], st));
+    if (i == SKYCELL_NUM_PHASES) g_prof.recorded = true;
+    return SKYCELL_OK;
+}
+
+#define SKYCELL_PROF(i)                             \
+    do {                                            \
+        int rc_ = prof_mark((i), st);               \
+        if (rc_ != SKYCELL_OK) return rc_;          \
+    } while (0)
+
+static int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
+                        int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
+                        uint64_t *stats, hipStream_t st)
+{
+    const GridDesc gd = make_grid(d, g);
+    Workspace ws;
+    workspace_layout(n, d, gd.cells, &ws, (char *)workspace);
+    int dev = 0;
+    SKYCELL_HIP_CHECK(hipGetDevice(&dev));
+    const int cus = device_cus(dev);
+    SKYCELL_PROF(0);
+    SKYCELL_HIP_CHECK(launch_init(ws, gd, stats, st));
+    SKYCELL_HIP_CHECK(launch_quantize_hist(points, dtype, n, gd, value_bits, ws, st));
+    SKYCELL_PROF(1);
+    SKYCELL_HIP_CHECK(launch_cell_prune(gd, ws, stats, st));
+    SKYCELL_PROF(2);
+    SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st));
+    SKYCELL_PROF(3);
+    SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, st));
+    SKYCELL_PROF(4);
+    SKYCELL_HIP_CHECK(launch_refine(n, gd, ws, stats, cus, st));
+    SKYCELL_PROF(5);
+    SKYCELL_HIP_CHECK(launch_output(n, ws, out_idx, out_count, stats, st));
+    SKYCELL_PROF(6);
+    return ok();
+}
+
+static int compute_owned(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
+                         int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *stream)
+{
+    int rc = validate(points, dtype, n, d, grid_res, value_bits, out_idx, out_count);
+    if (rc != SKYCELL_OK) return rc;
+    int g = 0;
+    if ((rc = resolve_grid(n, d, dtype, grid_res, &g)) != SKYCELL_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        SKYCELL_HIP_CHECK(launch_write_zero_count(out_count, st));
+        return ok();
+    }
+    const size_t need = workspace_layout(n, d, make_grid(d, g).cells, nullptr, nullptr);
+    int dev = 0;
+    SKYCELL_HIP_CHECK(hipGetDevice(&dev));
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        CachedWs &c = g_ws_cache[std::make_pair(dev, st)];
+        if (c.bytes < need) {
+            if (c.ptr != nullptr) {
+                SKYCELL_HIP_CHECK(hipStreamSynchronize(st));
+                SKYCELL_HIP_CHECK(hipFree(c.ptr));
+                c.ptr = nullptr;
+                c.bytes = 0;
+            }
+            if (hipMalloc(&c.ptr, need) != hipSuccess) {
+                c.ptr = nullptr;
+                return fail(SKYCELL_E_NOMEM, "hipMalloc of %zu workspace bytes failed", need);
+            }
+            c.bytes = need;
+        }
+        ptr = c.ptr;
+    }
+    return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, ptr, nullptr, st);
+}
+
+}  // namespace skycell
+
+using namespace skycell;
+
+extern "C" {
+
+int skycell_compute(const float *points, int64_t n, int32_t d, int32_t grid_res, int32_t *out_idx,
+                    int32_t *out_count, void *stream)
+{
+    return compute_owned(points, SKYCELL_DTYPE_F32, n, d, grid_res, 16, out_idx, out_count, stream);
+}
+
+int skycell_compute_u16(const uint16_t *points, int64_t n, int32_t d, int32_t grid_res,
+                        int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *stream)
+{
+    return compute_owned(points, SKYCELL_DTYPE_U16, n, d, grid_res, value_bits, out_idx, out_count,
+                         stream);
+}
+
+int skycell_workspace_bytes(int64_t n, int32_t d, int32_t grid_res, int32_t dtype, size_t *bytes)
+{
+    if (bytes == nullptr) return fail(SKYCELL_E_INVAL, "bytes is NULL");
+    if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16)
+        return fail(SKYCELL_E_INVAL, "dtype %d is not SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16", dtype);
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SKYCELL_E_INVAL, "n = %lld out of range", (long long)n);
+    if (d < 1 || d > SKYCELL_MAX_D) return fail(SKYCELL_E_INVAL, "d = %d is outside [1, %d]", d, SKYCELL_MAX_D);
+    if (grid_res < 0) return fail(SKYCELL_E_INVAL, "grid_res = %d is negative", grid_res);
+    int g = 0;
+    int rc = resolve_grid(n, d, dtype, grid_res, &g);
+    if (rc != SKYCELL_OK) return rc;
+    *bytes = n == 0 ? 256 : workspace_layout(n, d, make_grid(d, g).cells, nullptr, nullptr);
+    return ok();
+}
+
+int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
+                       int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
+                       size_t ws_bytes, uint64_t *stats, void *stream)
+{
+    if (dtype == SKYCELL_DTYPE_F32) value_bits = 16;
+    int rc = validate(points, dtype, n, d, grid_res, value_bits, out_idx, out_count);
+    if (rc != SKYCELL_OK) return rc;
+    int g = 0;
+    if ((rc = resolve_grid(n, d, dtype, grid_res, &g)) != SKYCELL_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        SKYCELL_HIP_CHECK(launch_write_zero_count(out_count, st));
+        return ok();
+    }
+    const size_t need = workspace_layout(n, d, make_grid(d, g).cells, nullptr, nullptr);
+    if (workspace == nullptr || ws_bytes < need)
+        return fail(SKYCELL_E_NOMEM, "workspace of %zu bytes is smaller than the %zu required",
+                    workspace ? ws_bytes : (size_t)0, need);
+    if (((uintptr_t)workspace & 255u) != 0) return fail(SKYCELL_E_INVAL, "workspace is not 256-byte aligned");
+    return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, workspace, stats, st);
+}
+
+int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res)
+{
+    if (grid_res == nullptr) return fail(SKYCELL_E_INVAL, "grid_res is NULL");
+    if (d < 1 || d > SKYCELL_MAX_D) return fail(SKYCELL_E_INVAL, "d = %d is outside [1, %d]", d, SKYCELL_MAX_D);
+    if (n < 0) return fail(SKYCELL_E_INVAL, "n is negative");
+    if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16)
+        return fail(SKYCELL_E_INVAL, "bad dtype %d", dtype);
+    *grid_res = choose_grid(n, d, dtype);
+    return ok();
+}
+
+int skycell_load_tuning(const char *path)
+{
+    std::vector<TuneEntry> entries;
+    if (path != nullptr) {
+        FILE *f = fopen(path, "r");
+        if (f == nullptr) return fail(SKYCELL_E_INVAL, "cannot open tuning table %s", path);
+        char line[256];
+        while (fgets(line, sizeof(line), f)) {
+            if (line[0] == '#') continue;
+            TuneEntry e;
+            if (sscanf(line, "%d %d %d %d", &e.d, &e.log2n, &e.dtype, &e.g) == 4 && e.d >= 1 &&
+                e.d <= SKYCELL_MAX_D && e.g >= 1)
+                entries.push_back(e);
+        }
+        fclose(f);
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.swap(entries);
+    return ok();
+}
+
+int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dtype, size_t *offsets,
+                             int32_t count)
+{
+    if (offsets == nullptr || count < 12) return fail(SKYCELL_E_INVAL, "offsets needs 12 entries");
+    if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16) return fail(SKYCELL_E_INVAL, "bad dtype %d", dtype);
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SKYCELL_E_INVAL, "n = %lld out of range", (long long)n);
+    if (d < 1 || d > SKYCELL_MAX_D) return fail(SKYCELL_E_INVAL, "d = %d is outside [1, %d]", d, SKYCELL_MAX_D);
+    if (grid_res < 0) return fail(SKYCELL_E_INVAL, "grid_res = %d is negative", grid_res);
+    int g = 0;
+    int rc = resolve_grid(n, d, dtype, grid_res, &g);
+    if (rc != SKYCELL_OK) return rc;
+    Workspace w;
+    char *const base = (char *)(uintptr_t)4096;  // any aligned base; offsets are relative
+    const size_t total = workspace_layout(n, d, make_grid(d, g).cells, &w, base);
+    const void *ptrs[11] = {w.cell_of, w.cnt, w.lc, w.info, w.offs, w.keys, w.sidx, w.items, w.flag,
+                            w.block_sums, w.ctr};
+    for (int i = 0; i < 11; ++i) offsets[i] = (size_t)((const char *)ptrs[i] - base);
+    offsets[11] = total;
+    return ok();
+}
+
+int skycell_profile_enable(int32_t on)
+{
+    if (!on) prof_free();
+    g_prof.on = on != 0;
+    return ok();
+}
+
+int skycell_profile_read(float *ms, int32_t count)
+{
+    if (ms == nullptr || count < SKYCELL_NUM_PHASES) return fail(SKYCELL_E_INVAL, "ms needs %d entries", SKYCELL_NUM_PHASES);
+    if (!g_prof.recorded) return fail(SKYCELL_E_INVAL, "no profiled call on this thread");
+    SKYCELL_HIP_CHECK(hipEventSynchronize(g_prof.ev[SKYCELL_NUM_PHASES]));
+    for (int i = 0; i < SKYCELL_NUM_PHASES; ++i) {
+        float v = 0.f;
+        SKYCELL_HIP_CHECK(hipEventElapsedTime(&v, g_prof.ev[i], g_prof.ev[i + 1]));
+        ms[i] = v;
+    }
+    return ok();
+}
+
+const char *skycell_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

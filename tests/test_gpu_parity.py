@@ -1,0 +1,261 @@
+"""Parity of the HIP skyline path with the CPU oracle.
+
+Every comparison is exact: the skyline is a unique index set, returned in
+ascending order, so the GPU and oracle arrays must be byte-identical.  Inputs
+are seeded synthetic data (see paper_2107_09993_amd.datagen).
+"""
+import ctypes
+import itertools
+
+import numpy as np
+import pytest
+
+import paper_2107_09993_amd as sky
+from paper_2107_09993_amd import datagen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def gpu_skyline(x, grid_res=0, value_bits=10, stats=False):
+    """Run the library on a host array [n, d] (float32 or uint16)."""
+    dev = _dev()
+    t = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
+    n, d = x.shape
+    s = sky.Skyline(n, d, dtype="f32" if x.dtype == np.float32 else "u16", grid_res=grid_res,
+                    value_bits=value_bits, device=dev, stats=stats)
+    s.run(t)
+    out = s.result().cpu().numpy()
+    if stats:
+        return out, s.stats_dict()
+    return out
+
+
+def check(x, oracle_mod, grid_res=0, value_bits=10, ref=None):
+    got = gpu_skyline(x, grid_res=grid_res, value_bits=value_bits)
+    if ref is None:
+        ref = oracle_mod.skyline_sfs(x)
+    assert got.dtype == np.int32
+    assert np.array_equal(got, ref), (len(got), len(ref))
+    return got
+
+
+# ---------------------------------------------------------------- small configs
+def test_restaurants(oracle_mod):
+    pts = np.asarray([[12, 9, 3], [8, 3, 2], [10, 17, 4], [26, 8, 1]], dtype=np.float32)
+    for g in (0, 1, 2, 4, 8):
+        assert gpu_skyline(pts, grid_res=g).tolist() == [1, 3]
+    assert gpu_skyline(pts.astype(np.uint16), grid_res=4, value_bits=5).tolist() == [1, 3]
+
+
+def test_independent_10k_d4_g8(oracle_mod):
+    """Plain SkyCell, n = 10,000, d = 4, i.i.d. uniform, seed 0, 8 cells per dimension."""
+    x = datagen.independent(10_000, 4, seed=0)
+    ref = oracle_mod.skyline_bruteforce(x)
+    assert np.array_equal(ref, oracle_mod.skyline_sfs(x))
+    got, st = gpu_skyline(x, grid_res=8, stats=True)
+    assert np.array_equal(got, ref)
+    assert st["grid_res"] == 8
+    assert st["skyline"] == len(ref)
+    assert st["surviving_cells"] <= 8 ** 4 - 7 ** 4  # Equation 14 bound
+    assert st["surviving_cells"] <= st["nonempty_cells"]
+
+
+@pytest.mark.parametrize("g", [1, 2, 3, 5, 7, 8, 16, 0])
+def test_grid_resolution_invariance(oracle_mod, g):
+    x = datagen.anticorrelated(6_000, 4, seed=3)
+    check(x, oracle_mod, grid_res=g)
+
+
+@pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 10, 12, 16])
+def test_distributions_and_dims(oracle_mod, dist, d):
+    n = 4_099 + 37 * d  # ragged: not a multiple of any tile
+    x = datagen.generate(dist, n, d, seed=d)
+    ref = oracle_mod.skyline_sfs(x)
+    check(x, oracle_mod, grid_res=0, ref=ref)
+    g = 3 if d <= 12 else 2
+    check(x, oracle_mod, grid_res=g, ref=ref)
+
+
+@pytest.mark.parametrize("d,high", [(2, 3), (3, 4), (6, 4), (6, 1024), (9, 3)])
+def test_u16_ties(oracle_mod, d, high):
+    rng = np.random.default_rng(d * 100 + high)
+    x = rng.integers(0, high, size=(8_000, d)).astype(np.uint16)
+    bits = max(1, int(np.ceil(np.log2(high))))
+    ref = oracle_mod.skyline_sfs(x)
+    for g in (0, 2, 4):
+        check(x, oracle_mod, grid_res=g, value_bits=bits, ref=ref)
+
+
+def test_u16_quantised_anticorrelated(oracle_mod):
+    x = datagen.quantise_u16(datagen.anticorrelated(40_000, 6, seed=1))
+    ref = oracle_mod.skyline_sfs(x)
+    for g in (0, 8, 16):
+        check(x, oracle_mod, grid_res=g, value_bits=10, ref=ref)
+
+
+def test_float_ties_and_duplicates(oracle_mod):
+    x = datagen.small_integers(10_000, 4, seed=5, high=5) * np.float32(0.25)
+    ref = check(x, oracle_mod, grid_res=4)
+    check(x, oracle_mod, grid_res=0, ref=ref)
+    base = datagen.anticorrelated(3_000, 5, seed=9)
+    dup = np.concatenate([base, base[::3], base[::7]], axis=0)
+    check(dup, oracle_mod, grid_res=4)
+
+
+def test_special_values(oracle_mod):
+    rng = np.random.default_rng(7)
+    x = datagen.independent(5_000, 3, seed=7) * np.float32(3.0) - np.float32(1.0)  # outside [0, 1)
+    specials = np.asarray([0.0, -0.0, np.inf, -np.inf, 1e-45, -1e-45, 1e-39, 1.0, 3e38],
+                          dtype=np.float32)
+    pick = rng.integers(0, len(specials), size=x.shape)
+    mask = rng.random(x.shape) < 0.05
+    x[mask] = specials[pick[mask]]
+    x[100] = [-0.0, 0.5, 0.5]
+    x[101] = [0.0, 0.5, 0.5]   # equal to x[100]: neither dominates
+    for g in (0, 1, 4, 8):
+        check(x, oracle_mod, grid_res=g)
+
+
+def test_nan_reported(oracle_mod):
+    x = datagen.independent(1_000, 3, seed=1)
+    x[10, 2] = np.nan
+    with pytest.raises(sky.SkycellError) as ei:
+        gpu_skyline(x)
+    assert ei.value.code == sky.E_NAN
+
+
+def test_empty_and_single(oracle_mod):
+    assert gpu_skyline(np.zeros((0, 3), dtype=np.float32)).size == 0
+    assert gpu_skyline(np.asarray([[0.4, 0.1]], dtype=np.float32)).tolist() == [0]
+    same = np.tile(np.asarray([[0.4, 0.1, 0.7]], dtype=np.float32), (300, 1))
+    assert gpu_skyline(same, grid_res=4).tolist() == list(range(300))
+
+
+def test_point_below_all(oracle_mod):
+    x = datagen.independent(20_000, 6, seed=2) + np.float32(0.001)
+    x[[5, 19_000]] = 0.0
+    assert gpu_skyline(x).tolist() == [5, 19_000]
+
+
+def test_exhaustive_tiny(oracle_mod):
+    vals = [0.0, 1.0, 2.0]
+    cells = list(itertools.product(vals, repeat=2))
+    for m in range(1, 4):
+        for combo in itertools.combinations_with_replacement(range(len(cells)), m):
+            pts = np.asarray([cells[c] for c in combo], dtype=np.float32)
+            ref = oracle_mod.skyline_pure_python(pts)
+            assert np.array_equal(gpu_skyline(pts, grid_res=2), ref)
+
+
+def test_invariants_permutations(oracle_mod):
+    x = datagen.anticorrelated(30_000, 6, seed=11)
+    base = gpu_skyline(x)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(x.shape[0])
+    assert np.array_equal(np.sort(perm[gpu_skyline(x[perm])]), base)
+    dp = rng.permutation(6)
+    assert np.array_equal(gpu_skyline(np.ascontiguousarray(x[:, dp])), base)
+    assert np.array_equal(gpu_skyline(x * np.float32(0.5)), base)
+    assert np.array_equal(base, oracle_mod.skyline_sfs(x))
+
+
+def test_deterministic_repeat(oracle_mod):
+    x = datagen.anticorrelated(200_000, 8, seed=4)
+    a = gpu_skyline(x, grid_res=8)
+    b = gpu_skyline(x, grid_res=8)
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- intermediate steps
+def test_quantiser_and_cell_prune_intermediates(oracle_mod):
+    """K1 cell ids bit-exact with the oracle's Equation 1, K3 surviving flags equal to
+    brute-force Definition 3 over the non-empty cells."""
+    dev = _dev()
+    for x, g in ((datagen.anticorrelated(20_000, 3, seed=1), 16),
+                 (datagen.independent(20_000, 4, seed=2), 5),
+                 (datagen.correlated(20_000, 5, seed=3), 4)):
+        n, d = x.shape
+        s = sky.Skyline(n, d, grid_res=g, device=dev)
+        s.run(torch.from_numpy(np.ascontiguousarray(x.T)).to(dev))
+        torch.cuda.synchronize()
+        offs = (ctypes.c_size_t * 12)()
+        assert sky.lib().skycell_workspace_layout(n, d, g, 0, offs, 12) == 0
+        ws = s.workspace.cpu().numpy()
+        cell_of = ws[offs[0]:offs[0] + 4 * n].view(np.uint32)
+        info = ws[offs[3]:offs[3] + 4 * g ** d].view(np.uint32)
+        coords = oracle_mod.cell_coords(x, g)
+        ref_cell = (coords.astype(np.int64) * (g ** np.arange(d))).sum(axis=1)
+        assert np.array_equal(cell_of.astype(np.int64), ref_cell)
+        ne = np.unique(ref_cell)
+        ne_coords = np.stack([(ne // g ** k) % g for k in range(d)], axis=1).astype(np.int32)
+        dom = oracle_mod.cells_dominated(ne_coords)
+        surv_gpu = (info >> 31).astype(bool)
+        expect = np.zeros(g ** d, dtype=bool)
+        expect[ne[~dom]] = True
+        assert np.array_equal(surv_gpu, expect)
+        assert expect.sum() <= g ** d - (g - 1) ** d  # Equation 14 (E6 bound)
+    # the worked example of Equation 1
+    p = np.asarray([[0.08, 0.63]], dtype=np.float32)
+    for g, want in ((8, 0 + 5 * 8), (16, 1 + 10 * 16)):
+        s = sky.Skyline(1, 2, grid_res=g, device=dev)
+        s.run(torch.from_numpy(np.ascontiguousarray(p.T)).to(dev))
+        torch.cuda.synchronize()
+        offs = (ctypes.c_size_t * 12)()
+        sky.lib().skycell_workspace_layout(1, 2, g, 0, offs, 12)
+        assert int(s.workspace.cpu().numpy()[offs[0]:offs[0] + 4].view(np.uint32)[0]) == want
+
+
+# ---------------------------------------------------------------- larger configs
+@pytest.mark.parametrize("dist", ["correlated", "independent"])
+def test_1m_d8_full(oracle_mod, dist):
+    """n = 1,000,000, d = 8; full oracle comparison (sort-first skyline)."""
+    x = datagen.generate(dist, 1_000_000, 8, seed=0)
+    check(x, oracle_mod, grid_res=0)
+    check(x, oracle_mod, grid_res=4)
+
+
+def _sampled(oracle_mod, x, got, n_in=250, n_out=250, seed=0):
+    rng = np.random.default_rng(seed)
+    n = x.shape[0]
+    flag = np.zeros(n, dtype=bool)
+    flag[got] = True
+    assert np.all(np.diff(got) > 0)
+    ins = got[rng.integers(0, len(got), size=min(n_in, len(got)))] if len(got) else np.zeros(0, int)
+    outs_all = np.nonzero(~flag)[0]
+    outs = outs_all[rng.integers(0, len(outs_all), size=min(n_out, len(outs_all)))] if len(outs_all) else np.zeros(0, int)
+    rand = rng.integers(0, n, size=200)
+    idx = np.concatenate([ins, outs, rand]).astype(np.int64)
+    res = oracle_mod.is_skyline(x, idx)
+    assert np.array_equal(res, flag[idx])
+
+
+def test_1m_d8_anticorrelated_sampled(oracle_mod):
+    x = datagen.anticorrelated(1_000_000, 8, seed=0)
+    got = gpu_skyline(x, grid_res=0)
+    _sampled(oracle_mod, x, got)
+    assert np.array_equal(gpu_skyline(x, grid_res=4), got)
+
+
+def test_headline_10m_d8_anticorrelated_sampled(oracle_mod):
+    """The benchmark workload and launch configuration: n = 10^7, d = 8,
+    anti-correlated, seed 0, grid chosen by the library (8 per dimension)."""
+    x = datagen.anticorrelated(10_000_000, 8, seed=0)
+    got, st = gpu_skyline(x, grid_res=0, stats=True)
+    assert st["grid_res"] == 8
+    assert st["skyline"] == len(got)
+    _sampled(oracle_mod, x, got, n_in=200, n_out=200)
+
+
+def test_u16_10m_d6_sampled(oracle_mod):
+    """n = 10^7, d = 6, anti-correlated quantised to 0..1023: ties everywhere."""
+    x = datagen.quantise_u16(datagen.anticorrelated(10_000_000, 6, seed=0))
+    got = gpu_skyline(x, grid_res=0, value_bits=10)
+    _sampled(oracle_mod, x, got, n_in=200, n_out=200)
