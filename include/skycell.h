@@ -44,7 +44,7 @@ extern "C" {
 enum {
     SKYCELL_OK = 0,
     SKYCELL_E_INVAL = -1, /* null pointer, n < 0, n >= 2^31, d outside [1, 16], bad enum  */
-    SKYCELL_E_RANGE = -2, /* grid of g^d cells exceeds SKYCELL_MAX_CELLS, bad value_bits   */
+    SKYCELL_E_RANGE = -2, /* cell index space exceeds SKYCELL_MAX_CELLS, bad value_bits    */
     SKYCELL_E_NOMEM = -3, /* device allocation failed, or workspace smaller than required  */
     SKYCELL_E_HIP = -4,   /* a HIP runtime call or kernel launch failed                    */
     SKYCELL_E_NODEV = -5, /* no usable GPU                                                 */
@@ -77,8 +77,9 @@ enum {
  *   n         number of points, 0 <= n < 2^31.  n = 0 writes *out_count = 0.
  *   d         number of attributes, 1 <= d <= SKYCELL_MAX_D.
  *   grid_res  cells per dimension g >= 1 (the paper uses g = 2^rho, Section III);
- *             0 lets the library choose (skycell_choose_grid).  g^d must not
- *             exceed SKYCELL_MAX_CELLS.
+ *             0 lets the library choose (skycell_choose_grid).  Cells are
+ *             numbered in Morton order over r = ceil(log2 g) bits per dimension,
+ *             so 2^(r*d) must not exceed SKYCELL_MAX_CELLS.
  *   out_idx   device int32 [n], written.      out_count  device int32 [1], written.
  *   stream    hipStream_t or NULL.
  * The library keeps a workspace per (device, stream), grown on demand with
@@ -135,15 +136,20 @@ int skycell_load_tuning(const char *path);
  * Byte offsets of the workspace's sub-buffers for (n, d, grid_res) (grid_res 0 =
  * autotuned), for tests and tools that inspect intermediate results of a
  * skycell_compute_ws call.  offsets[0..count) receives, in this order:
- *   0 cell_of  uint32 [n]        cell of each input point (mixed radix, dim 0 fastest)
- *   1 cnt      uint32 [cells]    histogram (consumed by the scatter)
- *   2 lc       uint8  [cells]    lower closure of the occupancy
- *   3 info     uint32 [cells]    bit 31: surviving non-empty cell; bits 0..d-1: cone mask
- *   4 offs     uint32 [cells+1]  first sorted position of each surviving cell
+ *   0 cell_of  uint32 [n]        Morton index of each point's cell: bit b of column
+ *                                c[k] at index bit b*d + k, r = ceil(log2 g) bits
+ *   1 rank     uint32 [n]        position of the point among the points of its cell
+ *   2 cnt      uint32 [cells]    histogram, cells = 2^(r*d)
+ *   3 lc       uint8  [cells]    lower closure of the occupancy
+ *   4 rec      uint64 [cells+1]  per-cell record: bits 0-31 first sorted position,
+ *                                32-46 point count (saturated at 0x7FFF), 47-62 mask
+ *                                (bit k: the cone one column lower in dimension k
+ *                                holds a non-empty cell), 63 surviving non-empty cell
  *   5 keys     uint32 [n*d]      sorted surviving points as order-preserving keys
- *   6 sidx     int32  [n]        original index of each sorted point
- *   7 items, 8 flag, 9 block sums, 10 counters, 11 total size.
- * count must be >= 12.  Returns SKYCELL_OK or an argument error.
+ *   6 fkeys    uint64 [n*ceil(d/8)]  7-bit screening columns, one byte per dimension
+ *   7 sidx     int32  [n]        original index of each sorted point
+ *   8 items, 9 flag, 10 block sums, 11 counters, 12 total size.
+ * count must be >= 13.  Returns SKYCELL_OK or an argument error.
  */
 int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dtype,
                              size_t *offsets, int32_t count);

@@ -104,8 +104,8 @@ def profile_read():
 
 
 def workspace_layout(n, d, grid_res=0, dtype=DTYPE_F32):
-    offs = (ctypes.c_size_t * 12)()
-    _check(lib().skycell_workspace_layout(int(n), int(d), int(grid_res), int(dtype), offs, 12))
+    offs = (ctypes.c_size_t * 13)()
+    _check(lib().skycell_workspace_layout(int(n), int(d), int(grid_res), int(dtype), offs, 13))
     return list(offs)
 
 

@@ -11,35 +11,81 @@ constexpr int kMaxD = 16;
 constexpr uint32_t kMaxCells = 1u << 26;
 constexpr int kWave = 64;
 
-// Bit of a cell-info word marking a surviving non-empty cell: it holds points
-// and no non-empty cell has a smaller column in every dimension (Definition 3).
-constexpr uint32_t kOccBit = 1u << 31;
-// Low kMaxD bits of the info word: bit k set iff the cell one column lower in
-// dimension k exists and some non-empty cell lies in its lower cone.
-constexpr uint32_t kNbrMask = (1u << kMaxD) - 1u;
+// Per-cell record, one 64-bit word per cell of the index space (plus one
+// sentinel), read with a single load by the refine's cone walk:
+//   bits  0..31  first sorted position of the cell's surviving points
+//   bits 32..46  number of those points, saturated at kRecCountSat (then the
+//                end is the next record's start)
+//   bits 47..62  lower-neighbour mask: bit k set iff the cell one column lower
+//                in dimension k exists and some non-empty cell lies in its
+//                lower cone
+//   bit  63      surviving non-empty cell: it holds points and no non-empty
+//                cell has a smaller column in every dimension (Definition 3)
+constexpr uint32_t kRecCountSat = 0x7FFFu;
+__host__ __device__ __forceinline__ uint32_t rec_start(uint64_t r) { return (uint32_t)r; }
+__host__ __device__ __forceinline__ uint32_t rec_count(uint64_t r) { return (uint32_t)(r >> 32) & kRecCountSat; }
+__host__ __device__ __forceinline__ uint32_t rec_nbr(uint64_t r) { return (uint32_t)(r >> 47) & 0xFFFFu; }
+__host__ __device__ __forceinline__ bool rec_surv(uint64_t r) { return (r >> 63) != 0u; }
+
+// Coarse screening keys: every coordinate also gets a 7-bit column on a
+// 128-column grid (same non-decreasing map as the cell columns), packed one
+// byte per dimension, eight dimensions per 64-bit word.  q can dominate p only
+// if every screening column of q is <= that of p.
+constexpr int kFineCols = 128;
+__host__ __device__ constexpr int fine_words(int d) { return (d + 7) / 8; }
 
 // Query points per refine work item, by dimensionality.
 __host__ __device__ constexpr int items_per_group(int d) { return d <= 8 ? 4 : 2; }
 
-// Regular grid of g columns per dimension, cells numbered in mixed radix with
-// dimension 0 fastest: x = sum_k c[k] * g^k.
+// Number of XCDs (each with its own L2) that workgroups are spread over
+// round-robin; the refine gives each one a contiguous share of the work.
+constexpr int kNumXcd = 8;
+
+// Regular grid of g columns per dimension.  Cells are numbered in Morton (Z)
+// order over r = ceil(log2 g) bits per dimension: bit b of column c[k] sits at
+// index bit b*d + k.  Cells with a column >= g exist in the index space but
+// never hold points.  Morton order is one of the cell orders the paper allows
+// (Algorithm 1 sorts points by cell "in any order, e.g. Z-order") and keeps
+// cells that are close in every dimension close in memory.
 struct GridDesc {
     int32_t d;
-    int32_t g;
-    uint32_t cells;            // g^d
-    uint32_t stride[kMaxD];    // g^k
-    uint32_t diag;             // sum_k g^k: x - diag is the cell one column lower everywhere
-    int32_t log_w;             // log2 of the bit width of one lane-cone offset field
+    int32_t g;                 // columns per dimension
+    int32_t r;                 // index bits per dimension
+    uint32_t cells;            // 2^(r*d): size of the index space
+    uint32_t mask[kMaxD];      // index bits that hold dimension k
 };
+
+// Index of the cell one column lower / higher in the dimension whose bits are
+// `m`.  Valid only when that column exists.
+__host__ __device__ __forceinline__ uint32_t morton_dec(uint32_t x, uint32_t m)
+{
+    return (((x & m) - 1u) & m) | (x & ~m);
+}
+__host__ __device__ __forceinline__ uint32_t morton_inc(uint32_t x, uint32_t m)
+{
+    return (((x | ~m) + 1u) & m) | (x & ~m);
+}
+// Spread the low bits of v over the set bits of m (lowest first).
+__host__ __device__ __forceinline__ uint32_t deposit_bits(uint32_t v, uint32_t m)
+{
+    uint32_t out = 0u;
+    for (uint32_t bit = 1u; m != 0u; bit <<= 1) {
+        const uint32_t low = m & (0u - m);
+        if (v & bit) out |= low;
+        m ^= low;
+    }
+    return out;
+}
 
 // Device scratch carved out of one workspace allocation.
 struct Workspace {
     uint32_t *cell_of;    // [n]     cell of each input point
-    uint32_t *cnt;        // [cells] points per cell; later the scatter cursor
+    uint32_t *rank;       // [n]     position of each point among the points of its cell
+    uint32_t *cnt;        // [cells] points per cell
     uint8_t *lc;          // [cells] lower closure: some non-empty cell <= this one
-    uint32_t *info;       // [cells] kOccBit | lower-neighbour mask
-    uint32_t *offs;       // [cells + 1] first sorted position of each surviving cell
+    uint64_t *rec;        // [cells + 1] cell records (see above)
     uint32_t *keys;       // [n * d] order-preserving keys of surviving points, AoS, sorted by cell
+    uint64_t *fkeys;      // [n * fine_words(d)] packed screening columns, same order
     int32_t *sidx;        // [n]     original index of each sorted surviving point
     uint2 *items;         // [n]     refine work items
     uint8_t *flag;        // [n]     1 = skyline, by original index
@@ -48,11 +94,11 @@ struct Workspace {
 };
 
 enum CtrIndex {
-    kCtrHead = 0,      // refine work-queue head
-    kCtrItems = 1,     // number of refine work items
-    kCtrErr = 2,       // nonzero: NaN seen in the input
-    kCtrSurvPts = 3,   // number of surviving points
-    kCtrCount = 8      // number of 32-bit counters reserved
+    kCtrItems = 0,     // number of refine work items
+    kCtrErr = 1,       // nonzero: NaN seen in the input
+    kCtrSurvPts = 2,   // number of surviving points
+    kCtrHead = 8,      // kNumXcd refine work-queue heads, one per XCD share
+    kCtrCount = 16     // number of 32-bit counters reserved
 };
 
 size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *base);
@@ -64,7 +110,7 @@ hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const Gri
 hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st);
 hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st);
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
-                          const Workspace &ws, hipStream_t st);
+                          const Workspace &ws, int value_bits, hipStream_t st);
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st);
 hipError_t launch_output(int64_t n, const Workspace &ws, int32_t *out_idx, int32_t *out_count,

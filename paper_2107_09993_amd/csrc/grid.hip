@@ -1,7 +1,7 @@
 // Grid phase of the skyline path (SkyCell paper, Section III grid structure and
 // Section V, Algorithm 1 line 1):
-//   K1  quantise every point to its cell (Equation 1) and build the occupancy
-//       histogram;
+//   K1  quantise every point to its cell (Equation 1), build the occupancy
+//       histogram and keep each point's rank inside its cell;
 //   K3  lower closure of the occupancy by d prefix-OR passes, then per cell the
 //       "dominated" test of Definition 3 and the lower-neighbour mask used by the
 //       refine's cone walk;
@@ -31,7 +31,8 @@ __global__ __launch_bounds__(kThreads) void k_init(uint32_t *cnt, uint32_t cells
     const uint32_t stride = gridDim.x * kThreads;
     for (uint32_t i = gid; i < cells; i += stride) cnt[i] = 0u;
     if (gid < kCtrCount) ctr[gid] = 0u;
-    if (stats != nullptr && gid < SKYCELL_NUM_STATS) stats[gid] = gid == SKYCELL_STAT_GRID_RES ? (uint64_t)g : 0ull;
+    if (stats != nullptr && gid < SKYCELL_NUM_STATS)
+        stats[gid] = gid == SKYCELL_STAT_GRID_RES ? (uint64_t)g : 0ull;
 }
 
 hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats, hipStream_t st)
@@ -69,6 +70,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict__ pts, uint32_t n,
                                                             GridDesc gd, int value_bits,
                                                             uint32_t *__restrict__ cell_of,
+                                                            uint32_t *__restrict__ rank,
                                                             uint32_t *__restrict__ cnt,
                                                             uint32_t *__restrict__ ctr)
 {
@@ -84,10 +86,10 @@ __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict_
             c = column_f32(v, gf, (uint32_t)gd.g, nan);
         else
             c = column_u16(v, (uint32_t)gd.g, value_bits);
-        cell += c * gd.stride[k];
+        cell |= deposit_bits(c, gd.mask[k]);
     }
     cell_of[i] = cell;
-    atomicAdd(&cnt[cell], 1u);
+    rank[i] = atomicAdd(&cnt[cell], 1u);
     if (nan) atomicOr(&ctr[kCtrErr], 1u);
 }
 
@@ -96,11 +98,12 @@ hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const Gri
 {
     if (dtype == SKYCELL_DTYPE_F32)
         hipLaunchKernelGGL(k_quantize_hist<float>, grid_for(n), dim3(kThreads), 0, st,
-                           (const float *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.cnt, ws.ctr);
+                           (const float *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.rank,
+                           ws.cnt, ws.ctr);
     else
         hipLaunchKernelGGL(k_quantize_hist<uint16_t>, grid_for(n), dim3(kThreads), 0, st,
-                           (const uint16_t *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.cnt,
-                           ws.ctr);
+                           (const uint16_t *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.rank,
+                           ws.cnt, ws.ctr);
     return hipGetLastError();
 }
 
@@ -114,48 +117,53 @@ __global__ __launch_bounds__(kThreads) void k_lc_init(const uint32_t *__restrict
     if (x < cells) lc[x] = cnt[x] != 0u ? 1 : 0;
 }
 
-// One thread per line of cells that differ only in dimension k.
+// One thread per line of cells that differ only in the dimension whose index
+// bits are `m`; the line is walked from column 0 up to column g-1.
 __global__ __launch_bounds__(kThreads) void k_lc_prefix(uint8_t *__restrict__ lc, uint32_t lines,
-                                                        uint32_t stride, uint32_t g)
+                                                        uint32_t m, uint32_t all_bits, uint32_t g)
 {
     const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
     if (t >= lines) return;
-    const uint32_t lo = t % stride, hi = t / stride;
-    uint32_t x = hi * stride * g + lo;
+    uint32_t x = deposit_bits(t, all_bits & ~m);
     uint8_t v = 0;
-    for (uint32_t j = 0; j < g; ++j, x += stride) {
+    for (uint32_t j = 0; j < g; ++j) {
         v |= lc[x];
         lc[x] = v;
+        if (j + 1 < g) x = morton_inc(x, m);
     }
 }
 
-// Per cell: the surviving flag and the lower-neighbour mask.
+// Per cell: the surviving flag, the lower-neighbour mask and the (saturated)
+// point count, written as the high half of the cell record; the scan fills in
+// the low half (first sorted position).
 //   dominated(x)  iff  every column of x is >= 1 and lc[x - (1,...,1)] = 1,
 //   i.e. a non-empty cell has a smaller column in every dimension (Definition 3).
-//   nbr bit k     iff  column k of x is >= 1 and lc[x - e_k] = 1, i.e. the cone
+//   mask bit k    iff  column k of x is >= 1 and lc[x - e_k] = 1, i.e. the cone
 //                      below x - e_k still holds a non-empty cell.
-__global__ __launch_bounds__(kThreads) void k_cell_info(GridDesc gd, const uint32_t *__restrict__ cnt,
-                                                        const uint8_t *__restrict__ lc,
-                                                        uint32_t *__restrict__ info,
-                                                        uint64_t *__restrict__ stats)
+__global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32_t *__restrict__ cnt,
+                                                       const uint8_t *__restrict__ lc,
+                                                       uint64_t *__restrict__ rec,
+                                                       uint64_t *__restrict__ stats)
 {
     const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
     bool occ = false, surv = false;
     if (x < gd.cells) {
-        uint32_t rem = x, nbr = 0u;
+        uint32_t nbr = 0u, diag = x;
         bool all_pos = true;
         for (int k = 0; k < gd.d; ++k) {
-            const uint32_t c = rem % (uint32_t)gd.g;
-            rem /= (uint32_t)gd.g;
-            if (c == 0u) {
+            const uint32_t m = gd.mask[k];
+            if ((x & m) == 0u) {
                 all_pos = false;
-            } else if (lc[x - gd.stride[k]]) {
-                nbr |= 1u << k;
+            } else {
+                if (lc[morton_dec(x, m)]) nbr |= 1u << k;
+                diag = morton_dec(diag, m);
             }
         }
-        occ = cnt[x] != 0u;
-        surv = occ && !(all_pos && lc[x - gd.diag]);
-        info[x] = nbr | (surv ? kOccBit : 0u);
+        const uint32_t c = cnt[x];
+        occ = c != 0u;
+        surv = occ && !(all_pos && lc[diag]);
+        const uint64_t cs = surv ? (c < kRecCountSat ? c : kRecCountSat) : 0u;
+        rec[x] = ((uint64_t)(surv ? 1u : 0u) << 63) | ((uint64_t)nbr << 47) | (cs << 32);
     }
     if (stats != nullptr) {
         const uint64_t bo = __ballot(occ), bs = __ballot(surv);
@@ -171,14 +179,15 @@ __global__ __launch_bounds__(kThreads) void k_cell_info(GridDesc gd, const uint3
 hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st)
 {
     hipLaunchKernelGGL(k_lc_init, grid_for(gd.cells), dim3(kThreads), 0, st, ws.cnt, ws.lc, gd.cells);
-    const uint32_t lines = gd.cells / (uint32_t)gd.g;
     if (gd.g > 1) {
+        const uint32_t lines = gd.cells >> gd.r;
+        const uint32_t all_bits = gd.cells - 1u;
         for (int k = 0; k < gd.d; ++k)
             hipLaunchKernelGGL(k_lc_prefix, grid_for(lines), dim3(kThreads), 0, st, ws.lc, lines,
-                               gd.stride[k], (uint32_t)gd.g);
+                               gd.mask[k], all_bits, (uint32_t)gd.g);
     }
-    hipLaunchKernelGGL(k_cell_info, grid_for(gd.cells), dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
-                       ws.info, stats);
+    hipLaunchKernelGGL(k_cell_rec, grid_for(gd.cells), dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
+                       ws.rec, stats);
     return hipGetLastError();
 }
 
@@ -186,26 +195,27 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *
 // Scan value per cell: surviving points (low 32 bits) and refine work items
 // (high 32 bits); a cell with m surviving points gives ceil(m / M) items.
 struct CellLoader {
-    const uint32_t *info;
+    const uint64_t *rec;
     const uint32_t *cnt;
     uint32_t per_item;
     __device__ uint64_t operator()(uint64_t x) const
     {
-        const uint32_t m = (info[x] & kOccBit) ? cnt[x] : 0u;
+        const uint32_t m = rec_surv(rec[x]) ? cnt[x] : 0u;
         const uint32_t it = (m + per_item - 1u) / per_item;
         return (uint64_t)m | ((uint64_t)it << 32);
     }
 };
 
-// Item = (first sorted position, (point count << 26) | cell).
+// Writes the first sorted position into the low half of the cell record and
+// the cell's work items: (first sorted position, (point count << 26) | cell).
 struct CellEmitter {
-    uint32_t *offs;
+    uint32_t *rec_words;
     uint2 *items;
     uint32_t per_item;
     __device__ void operator()(uint64_t x, uint64_t prefix, uint64_t v) const
     {
         const uint32_t start = (uint32_t)prefix;
-        offs[x] = start;
+        rec_words[2 * x] = start;
         const uint32_t m = (uint32_t)v;
         const uint32_t it = (uint32_t)(v >> 32);
         const uint32_t ibase = (uint32_t)(prefix >> 32);
@@ -218,10 +228,10 @@ struct CellEmitter {
 };
 
 __global__ void k_cell_scan_total(const uint64_t *block_sums, uint32_t nb, uint32_t cells,
-                                  uint32_t *offs, uint32_t *ctr, uint64_t *stats)
+                                  uint64_t *rec, uint32_t *ctr, uint64_t *stats)
 {
     const uint64_t tot = block_sums[nb];
-    offs[cells] = (uint32_t)tot;
+    rec[cells] = (uint32_t)tot;  // sentinel: start of "the cell after the last"
     ctr[kCtrSurvPts] = (uint32_t)tot;
     ctr[kCtrItems] = (uint32_t)(tot >> 32);
     if (stats != nullptr) {
@@ -233,26 +243,29 @@ __global__ void k_cell_scan_total(const uint64_t *block_sums, uint32_t nb, uint3
 hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st)
 {
     const uint32_t m = (uint32_t)items_per_group(gd.d);
-    CellLoader ld{ws.info, ws.cnt, m};
-    CellEmitter em{ws.offs, ws.items, m};
+    CellLoader ld{ws.rec, ws.cnt, m};
+    CellEmitter em{(uint32_t *)ws.rec, ws.items, m};
     hipError_t e = enqueue_scan<uint64_t>(ld, em, gd.cells, ws.block_sums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cell_scan_total, dim3(1), dim3(1), 0, st, (const uint64_t *)ws.block_sums,
-                       scan_tiles(gd.cells), gd.cells, ws.offs, ws.ctr, stats);
+                       scan_tiles(gd.cells), gd.cells, ws.rec, ws.ctr, stats);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ K4
-// Counting-sort scatter of the points of surviving cells.  The slot inside a
-// cell comes from an atomic cursor, so the order inside a cell is arbitrary;
-// the skyline does not depend on it.  Also clears the output flag of every point.
+// Counting-sort scatter of the points of surviving cells: slot = first sorted
+// position of the cell + the point's rank from the histogram atomic, so the
+// order inside a cell follows the histogram's (arbitrary) order; the skyline
+// does not depend on it.  Writes the exact keys and the packed screening
+// columns, and clears the output flag of every point.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts, uint32_t n, int d,
+                                                      int value_bits,
                                                       const uint32_t *__restrict__ cell_of,
-                                                      const uint32_t *__restrict__ info,
-                                                      const uint32_t *__restrict__ offs,
-                                                      uint32_t *__restrict__ cnt,
+                                                      const uint32_t *__restrict__ rank,
+                                                      const uint64_t *__restrict__ rec,
                                                       uint32_t *__restrict__ keys,
+                                                      uint64_t *__restrict__ fkeys,
                                                       int32_t *__restrict__ sidx,
                                                       uint8_t *__restrict__ flag)
 {
@@ -260,30 +273,44 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts,
     if (i >= n) return;
     flag[i] = 0;
     const uint32_t x = cell_of[i];
-    if (!(info[x] & kOccBit)) return;
-    const uint32_t pos = offs[x] + atomicSub(&cnt[x], 1u) - 1u;
+    const uint64_t r = rec[x];
+    if (!rec_surv(r)) return;
+    const uint32_t pos = rec_start(r) + rank[i];
     uint32_t *dst = keys + (size_t)pos * d;
+    const int fw = fine_words(d);
+    uint64_t *fdst = fkeys + (size_t)pos * fw;
+    uint64_t word = 0ull;
+    bool nan = false;
     for (int k = 0; k < d; ++k) {
         const T v = pts[(size_t)k * n + i];
-        if constexpr (sizeof(T) == 4)
+        uint32_t f;
+        if constexpr (sizeof(T) == 4) {
             dst[k] = f32_key(v);
-        else
+            f = column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan);
+        } else {
             dst[k] = (uint32_t)v;
+            f = column_u16(v, (uint32_t)kFineCols, value_bits);
+        }
+        word |= (uint64_t)f << (8 * (k & 7));
+        if ((k & 7) == 7 || k == d - 1) {
+            fdst[k >> 3] = word;
+            word = 0ull;
+        }
     }
     sidx[pos] = (int32_t)i;
 }
 
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
-                          const Workspace &ws, hipStream_t st)
+                          const Workspace &ws, int value_bits, hipStream_t st)
 {
     if (dtype == SKYCELL_DTYPE_F32)
         hipLaunchKernelGGL(k_scatter<float>, grid_for(n), dim3(kThreads), 0, st, (const float *)pts,
-                           (uint32_t)n, gd.d, ws.cell_of, ws.info, ws.offs, ws.cnt, ws.keys, ws.sidx,
-                           ws.flag);
+                           (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank, ws.rec, ws.keys, ws.fkeys,
+                           ws.sidx, ws.flag);
     else
         hipLaunchKernelGGL(k_scatter<uint16_t>, grid_for(n), dim3(kThreads), 0, st,
-                           (const uint16_t *)pts, (uint32_t)n, gd.d, ws.cell_of, ws.info, ws.offs,
-                           ws.cnt, ws.keys, ws.sidx, ws.flag);
+                           (const uint16_t *)pts, (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank,
+                           ws.rec, ws.keys, ws.fkeys, ws.sidx, ws.flag);
     return hipGetLastError();
 }
 

@@ -47,15 +47,20 @@ struct TuneEntry {
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
 
-// g^d with saturation above the cell budget.
+// Index bits per dimension for g columns: ceil(log2 g).
+static int index_bits(int g)
+{
+    int r = 0;
+    while ((1 << r) < g) ++r;
+    return r;
+}
+
+// Size of the Morton index space, 2^(r*d), saturated above the cell budget.
 static uint64_t cells_of(int g, int d)
 {
-    uint64_t c = 1;
-    for (int k = 0; k < d; ++k) {
-        c *= (uint64_t)g;
-        if (c > (uint64_t)kMaxCells) return (uint64_t)kMaxCells + 1;
-    }
-    return c;
+    const int r = index_bits(g);
+    if ((uint64_t)r * (uint64_t)d > 26) return (uint64_t)kMaxCells + 1;
+    return (uint64_t)1 << (r * d);
 }
 
 static int default_grid(int64_t n, int d)
@@ -94,19 +99,10 @@ static GridDesc make_grid(int d, int g)
     memset(&gd, 0, sizeof(gd));
     gd.d = d;
     gd.g = g;
-    uint32_t s = 1, diag = 0;
-    for (int k = 0; k < d; ++k) {
-        gd.stride[k] = s;
-        diag += s;
-        s *= (uint32_t)g;
-    }
-    gd.cells = s;
-    gd.diag = diag;
-    int bits = 1;
-    while (((uint64_t)1 << bits) <= (uint64_t)(g - 1)) ++bits;
-    int logw = 0;
-    while ((1 << logw) < bits) ++logw;
-    gd.log_w = logw;
+    gd.r = index_bits(g);
+    gd.cells = 1u << (gd.r * d);
+    for (int k = 0; k < d; ++k)
+        for (int b = 0; b < gd.r; ++b) gd.mask[k] |= 1u << (b * d + k);
     return gd;
 }
 
@@ -124,11 +120,12 @@ size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *b
     const size_t nn = (size_t)n;
     Workspace w;
     w.cell_of = (uint32_t *)take(4 * nn);
+    w.rank = (uint32_t *)take(4 * nn);
     w.cnt = (uint32_t *)take(4 * (size_t)cells);
     w.lc = (uint8_t *)take((size_t)cells);
-    w.info = (uint32_t *)take(4 * (size_t)cells);
-    w.offs = (uint32_t *)take(4 * ((size_t)cells + 1));
+    w.rec = (uint64_t *)take(8 * ((size_t)cells + 1));
     w.keys = (uint32_t *)take(4 * nn * (size_t)d);
+    w.fkeys = (uint64_t *)take(8 * nn * (size_t)fine_words(d));
     w.sidx = (int32_t *)take(4 * nn);
     w.items = (uint2 *)take(8 * nn);
     w.flag = (uint8_t *)take(nn);
@@ -186,8 +183,9 @@ static int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, i
 {
     const int g = grid_res > 0 ? grid_res : choose_grid(n, d, dtype);
     if (cells_of(g, d) > kMaxCells)
-        return fail(SKYCELL_E_RANGE, "grid of %d^%d cells exceeds the budget of %u cells", g, d,
-                    (unsigned)kMaxCells);
+        return fail(SKYCELL_E_RANGE,
+                    "grid of %d columns in %d dimensions needs 2^(%d*%d) cells, over the budget of %u",
+                    g, d, index_bits(g), d, (unsigned)kMaxCells);
     *g_out = g;
     return SKYCELL_OK;
 }
@@ -256,7 +254,7 @@ static int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d,
     SKYCELL_PROF(2);
     SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st));
     SKYCELL_PROF(3);
-    SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, st));
+    SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, value_bits, st));
     SKYCELL_PROF(4);
     SKYCELL_HIP_CHECK(launch_refine(n, gd, ws, stats, cus, st));
     SKYCELL_PROF(5);
@@ -393,7 +391,7 @@ int skycell_load_tuning(const char *path)
 int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dtype, size_t *offsets,
                              int32_t count)
 {
-    if (offsets == nullptr || count < 12) return fail(SKYCELL_E_INVAL, "offsets needs 12 entries");
+    if (offsets == nullptr || count < 13) return fail(SKYCELL_E_INVAL, "offsets needs 13 entries");
     if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16) return fail(SKYCELL_E_INVAL, "bad dtype %d", dtype);
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SKYCELL_E_INVAL, "n = %lld out of range", (long long)n);
     if (d < 1 || d > SKYCELL_MAX_D) return fail(SKYCELL_E_INVAL, "d = %d is outside [1, %d]", d, SKYCELL_MAX_D);
@@ -404,10 +402,10 @@ int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dty
     Workspace w;
     char *const base = (char *)(uintptr_t)4096;  // any aligned base; offsets are relative
     const size_t total = workspace_layout(n, d, make_grid(d, g).cells, &w, base);
-    const void *ptrs[11] = {w.cell_of, w.cnt, w.lc, w.info, w.offs, w.keys, w.sidx, w.items, w.flag,
-                            w.block_sums, w.ctr};
-    for (int i = 0; i < 11; ++i) offsets[i] = (size_t)((const char *)ptrs[i] - base);
-    offsets[11] = total;
+    const void *ptrs[12] = {w.cell_of, w.rank, w.cnt, w.lc, w.rec, w.keys, w.fkeys, w.sidx, w.items,
+                            w.flag, w.block_sums, w.ctr};
+    for (int i = 0; i < 12; ++i) offsets[i] = (size_t)((const char *)ptrs[i] - base);
+    offsets[12] = total;
     return ok();
 }
 

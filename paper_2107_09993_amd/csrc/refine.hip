@@ -10,19 +10,32 @@
 // cannot be dominated), and pruned points never need to be candidates because
 // whatever dominates them also dominates anything they dominate.
 //
-// Cone walk: the cells y <= x are enumerated as x - delta, delta >= 0, by a
-// depth-first walk that lowers dimensions in non-decreasing order (each cell is
-// reached by exactly one such path).  A step down in dimension k is taken only
-// if the info word of the current cell says that the cone below x - e_k still
-// holds a non-empty cell (lower-closure bit), which prunes the empty part of the
-// cone.  The walk keeps no stack: delta, packed in fixed-width fields, tells
-// which dimension to step back up in.
+// Cone walk.  With c the query cell, the cells y <= c are c - delta, delta >= 0,
+// visited in odometer order (delta[0] fastest).  From the current cell the next
+// one lowers the smallest dimension j that still can be lowered, after putting
+// dimensions below j back to c's columns: y = anchor_j - e_j, where anchor_j =
+// c - (0, .., 0, delta[j], delta[j+1], ..).  The lower closure is monotone, so
+// once the cone below anchor_j - e_j is empty every larger delta[j] is empty
+// too and the walk carries to j + 1.  Whether anchor_j - e_j is worth a visit
+// is bit j of anchor_j's lower-neighbour mask; the walk only keeps those d bits
+// ("diag"), refreshed from the record of every visited cell, so it never probes
+// an empty cone, never steps back up and holds O(1) state.
 //
-// Mapping: one lane owns one work item (up to M query points of one cell, their
-// keys in registers) and walks its cone; lanes whose item ends take new items
-// from a global queue, a batch per wave, so that unequal cone sizes do not idle
-// the wave.  Every loop turn a lane does one unit of work: test one candidate
-// point against its live query points, or one step of the walk.
+// Candidate tests.  Each candidate point is first screened with its packed
+// 7-bit columns (one 64-bit subtraction per eight dimensions tests q <= p in
+// every byte); only candidates that pass are compared exactly (Definition 1 on
+// order-preserving integer keys), one turn later.
+//
+// Mapping.  One lane owns one work item (up to M query points of one cell, in
+// registers) and runs its walk; lanes whose item ends take new items from a
+// queue, a batch per wave, so unequal cone sizes do not idle the wave.  Each
+// loop turn issues every load a lane needs (the next cell record, the screening
+// columns of up to two candidates, the exact keys of a deferred candidate) and
+// waits once.  Items are in Morton order of their cells and split into
+// kNumXcd contiguous shares with one queue each; workgroup b starts on share
+// b % kNumXcd (the XCD it is dispatched to), so the waves sharing an L2 work
+// on neighbouring cells and their cones, and moves on to the other shares once
+// its own is empty.
 #include "common.h"
 #include "../../include/skycell.h"
 
@@ -30,124 +43,222 @@ namespace skycell {
 
 constexpr int kRefineThreads = 256;
 constexpr int kRefillMin = 16;
+constexpr uint64_t kHigh = 0x8080808080808080ull;
 
 template <int D>
 __global__ __launch_bounds__(kRefineThreads) void k_refine(const uint32_t *__restrict__ keys,
+                                                           const uint64_t *__restrict__ fkeys,
                                                            const int32_t *__restrict__ sidx,
-                                                           const uint32_t *__restrict__ info,
-                                                           const uint32_t *__restrict__ offs,
+                                                           const uint64_t *__restrict__ rec,
                                                            const uint2 *__restrict__ items,
                                                            uint32_t *__restrict__ ctr,
                                                            uint8_t *__restrict__ flag, GridDesc gd,
                                                            uint64_t *__restrict__ stats)
 {
     constexpr int M = items_per_group(D);
-    __shared__ uint32_t s_stride[kMaxD];
-    if (threadIdx.x < kMaxD) s_stride[threadIdx.x] = threadIdx.x < (unsigned)D ? gd.stride[threadIdx.x] : 0u;
+    constexpr int FW = fine_words(D);
+    constexpr uint32_t kAll = (1u << D) - 1u;
+    __shared__ uint32_t s_mask[kMaxD], s_low[kMaxD];
+    if (threadIdx.x < kMaxD) {
+        uint32_t low = 0u;
+        for (int k = 0; k < (int)threadIdx.x && k < D; ++k) low |= gd.mask[k];
+        s_mask[threadIdx.x] = threadIdx.x < (unsigned)D ? gd.mask[threadIdx.x] : 0u;
+        s_low[threadIdx.x] = low;
+    }
     __syncthreads();
 
     const uint32_t n_items = ctr[kCtrItems];
-    const int logw = gd.log_w;
+    int share = (int)(blockIdx.x % kNumXcd);  // wave-uniform
+    int shares_left = kNumXcd;
     const int lane = __lane_id();
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
     uint32_t q[M][D];
+    uint64_t qf[M][FW];
 #pragma unroll
-    for (int t = 0; t < M; ++t)
+    for (int t = 0; t < M; ++t) {
 #pragma unroll
         for (int k = 0; k < D; ++k) q[t][k] = 0u;
-    uint32_t alive = 0u, qstart = 0u;
-    uint32_t x = 0u, nb = 0u, cur = 0u, end = 0u;
-    uint64_t delta = 0ull;
-    int mode = 0;  // 0 idle, 1 testing the points of the current cell, 2 walking the cone
-    bool exhausted = false;
+#pragma unroll
+        for (int w = 0; w < FW; ++w) qf[t][w] = kHigh;
+    }
+    uint32_t alive = 0u, qstart = 0u, qcnt = 0u;
+    uint32_t root = 0u, x = 0u, diag = 0u;
+    bool walking = false;
+    uint32_t cur = 0u, end = 0u, pcur = 0u, pend = 0u;
+    uint32_t ex = 0u, exmask = 0u;
+    bool active = false, exhausted = false;
     uint64_t visits = 0ull, tests = 0ull;
 
     for (;;) {
-        // ---- refill idle lanes from the global queue, a batch per wave
-        const bool wants = (mode == 0) && !exhausted;
+        // ---- refill idle lanes, a batch per wave
+        const bool wants = !active && !exhausted;
         const uint64_t want = __ballot(wants);
-        const uint64_t busy = __ballot(mode != 0);
+        const uint64_t busy = __ballot(active);
         if (want != 0ull && (__popcll(want) >= kRefillMin || busy == 0ull)) {
             const int leader = __ffsll((unsigned long long)want) - 1;
+            const uint32_t s_lo = (uint32_t)(((uint64_t)n_items * share) / kNumXcd);
+            const uint32_t s_hi = (uint32_t)(((uint64_t)n_items * (share + 1)) / kNumXcd);
             uint32_t base = 0u;
-            if (lane == leader) base = atomicAdd(&ctr[kCtrHead], (uint32_t)__popcll(want));
-            base = __shfl(base, leader);
+            if (lane == leader) base = atomicAdd(&ctr[kCtrHead + share], (uint32_t)__popcll(want));
+            base = __shfl(base, leader) + s_lo;
+            if (base + (uint32_t)__popcll(want) > s_hi) {
+                share = share + 1 == kNumXcd ? 0 : share + 1;
+                --shares_left;
+            }
             if (wants) {
                 const uint32_t my = base + (uint32_t)__popcll(want & below);
-                if (my < n_items) {
+                if (my < s_hi) {
                     const uint2 it = items[my];
-                    const uint32_t qc = it.y >> 26;
+                    qcnt = it.y >> 26;
                     qstart = it.x;
-                    x = it.y & ((1u << 26) - 1u);
+                    root = it.y & ((1u << 26) - 1u);
+                    const uint64_t r = rec[root];
 #pragma unroll
-                    for (int t = 0; t < M; ++t)
+                    for (int t = 0; t < M; ++t) {
+                        const bool has = t < (int)qcnt;
 #pragma unroll
-                        for (int k = 0; k < D; ++k)
-                            q[t][k] = (t < (int)qc) ? keys[(size_t)(qstart + t) * D + k] : 0u;
-                    alive = (1u << qc) - 1u;
-                    delta = 0ull;
-                    nb = info[x] & kNbrMask;
-                    cur = offs[x];
-                    end = offs[x + 1];
-                    mode = 1;
+                        for (int k = 0; k < D; ++k) q[t][k] = has ? keys[(size_t)(qstart + t) * D + k] : 0u;
+#pragma unroll
+                        for (int w = 0; w < FW; ++w)
+                            qf[t][w] = (has ? fkeys[(size_t)(qstart + t) * FW + w] : 0ull) | kHigh;
+                    }
+                    alive = (1u << qcnt) - 1u;
+                    x = root;
+                    diag = rec_nbr(r) & kAll;
+                    walking = true;
+                    cur = rec_start(r);
+                    uint32_t c = rec_count(r);
+                    if (c == kRecCountSat) c = rec_start(rec[root + 1]) - cur;
+                    end = cur + c;
+                    pcur = pend = 0u;
+                    exmask = 0u;
+                    active = true;
                     ++visits;
-                } else {
+                } else if (shares_left <= 0) {
                     exhausted = true;
                 }
             }
         }
-        if (__ballot(mode != 0) == 0ull) break;
+        if (__ballot(active) == 0ull) {
+            if (__ballot(!exhausted) == 0ull) break;  // every share is empty
+            continue;                                  // retry the refill on the next share
+        }
 
-        if (mode == 1) {
-            // ---- one candidate point against the live query points (Definition 1)
-            uint32_t c[D];
+        // ---- issue this turn's loads
+        const bool c0ok = active && cur < end;
+        const bool c1ok = active && cur + 1 < end;
+        uint64_t f0[FW], f1[FW];
 #pragma unroll
-            for (int k = 0; k < D; ++k) c[k] = keys[(size_t)cur * D + k];
+        for (int w = 0; w < FW; ++w) {
+            f0[w] = c0ok ? fkeys[(size_t)cur * FW + w] : 0ull;
+            f1[w] = c1ok ? fkeys[(size_t)(cur + 1) * FW + w] : 0ull;
+        }
+        const bool exok = active && exmask != 0u;
+        uint32_t e[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) e[k] = exok ? keys[(size_t)ex * D + k] : 0u;
+        bool stepped = false;
+        int j = 0;
+        uint32_t y = 0u;
+        uint64_t r = 0ull;
+        if (active && walking && pcur >= pend) {
+            if (diag == 0u) {
+                walking = false;
+            } else {
+                j = __ffs(diag) - 1;
+                y = morton_dec((x & ~s_low[j]) | (root & s_low[j]), s_mask[j]);
+                r = rec[y];
+                stepped = true;
+            }
+        }
+
+        // ---- deferred exact test (Definition 1)
+        if (exok) {
 #pragma unroll
             for (int t = 0; t < M; ++t) {
-                if (alive & (1u << t)) {
+                if ((exmask & alive) & (1u << t)) {
                     bool le = true, ne = false;
 #pragma unroll
                     for (int k = 0; k < D; ++k) {
-                        le = le && (c[k] <= q[t][k]);
-                        ne = ne || (c[k] != q[t][k]);
+                        le = le && (e[k] <= q[t][k]);
+                        ne = ne || (e[k] != q[t][k]);
                     }
                     if (le && ne) alive &= ~(1u << t);
-                    ++tests;
                 }
             }
-            ++cur;
-            if (alive == 0u)
-                mode = 0;  // every query point of the item is dominated
-            else if (cur == end)
-                mode = 2;
-        } else if (mode == 2) {
-            if (nb != 0u) {
-                // ---- step down in the lowest allowed dimension
-                const int k = __ffs(nb) - 1;
-                x -= s_stride[k];
-                delta += 1ull << (k << logw);
-                const uint32_t inf = info[x];
-                nb = inf & kNbrMask & ~((1u << k) - 1u);
-                ++visits;
-                if (inf & kOccBit) {
-                    cur = offs[x];
-                    end = offs[x + 1];
-                    mode = 1;
+            exmask = 0u;
+        }
+
+        // ---- screening of up to two candidates
+        if (c0ok) {
+            uint32_t adv = 0u;
+#pragma unroll
+            for (int cnd = 0; cnd < 2; ++cnd) {
+                if (cnd == 1 && !c1ok) break;
+                uint32_t pass = 0u;
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    if (alive & (1u << t)) {
+                        bool ok = true;
+#pragma unroll
+                        for (int w = 0; w < FW; ++w) {
+                            const uint64_t diff = qf[t][w] - (cnd == 0 ? f0[w] : f1[w]);
+                            ok = ok && ((diff & kHigh) == kHigh);
+                        }
+                        if (ok) pass |= 1u << t;
+                        ++tests;
+                    }
                 }
-            } else if (delta == 0ull) {
-                // ---- cone exhausted: the live query points are skyline points
+                if (pass == 0u) {
+                    ++adv;
+                    continue;
+                }
+                if (exmask == 0u) {
+                    ex = cur + (uint32_t)cnd;
+                    exmask = pass;
+                    ++adv;
+                    continue;
+                }
+                break;  // the exact slot is taken: screen this candidate again next turn
+            }
+            cur += adv;
+            if (cur >= end && pcur < pend) {
+                cur = pcur;
+                end = pend;
+                pcur = pend = 0u;
+            }
+        }
+
+        // ---- walk step: take the record of the new cell
+        if (stepped) {
+            x = y;
+            const uint32_t low = (2u << j) - 1u;
+            diag = (diag & ~low) | (rec_nbr(r) & low);
+            ++visits;
+            if (rec_surv(r)) {
+                const uint32_t s = rec_start(r);
+                uint32_t c = rec_count(r);
+                if (c == kRecCountSat) c = rec_start(rec[y + 1]) - s;
+                if (cur >= end) {
+                    cur = s;
+                    end = s + c;
+                } else {
+                    pcur = s;
+                    pend = s + c;
+                }
+            }
+        }
+
+        // ---- item end
+        if (active) {
+            if (alive == 0u) {
+                active = false;  // every query point of the item is dominated
+            } else if (!walking && cur >= end && pcur >= pend && exmask == 0u) {
 #pragma unroll
                 for (int t = 0; t < M; ++t)
                     if (alive & (1u << t)) flag[sidx[qstart + t]] = 1;
-                mode = 0;
-            } else {
-                // ---- step back up along the last lowered dimension
-                const int k = (63 - __clzll((long long)delta)) >> logw;
-                x += s_stride[k];
-                delta -= 1ull << (k << logw);
-                nb = info[x] & kNbrMask & ~((2u << k) - 1u);
+                active = false;
             }
         }
     }
@@ -177,8 +288,8 @@ static hipError_t launch_refine_d(const GridDesc &gd, const Workspace &ws, uint6
     }
     const unsigned blocks = (unsigned)(num_cus * blocks_per_cu);
     hipLaunchKernelGGL(k_refine<D>, dim3(blocks), dim3(kRefineThreads), 0, st,
-                       (const uint32_t *)ws.keys, (const int32_t *)ws.sidx, (const uint32_t *)ws.info,
-                       (const uint32_t *)ws.offs, (const uint2 *)ws.items, ws.ctr, ws.flag, gd, stats);
+                       (const uint32_t *)ws.keys, (const uint64_t *)ws.fkeys, (const int32_t *)ws.sidx,
+                       (const uint64_t *)ws.rec, (const uint2 *)ws.items, ws.ctr, ws.flag, gd, stats);
     return hipGetLastError();
 }
 

@@ -91,8 +91,9 @@ def test_workspace_bytes_grows_with_n_and_grid():
     c = sky.workspace_bytes(1000, 4, 16)
     assert a < b and a < c
     # layout offsets are increasing, aligned and end at the total
-    offs = (ctypes.c_size_t * 12)()
-    assert sky.lib().skycell_workspace_layout(1000, 4, 8, 0, offs, 12) == 0
+    offs = (ctypes.c_size_t * 13)()
+    assert sky.lib().skycell_workspace_layout(1000, 4, 8, 0, offs, 13) == 0
+    assert sky.lib().skycell_workspace_layout(1000, 4, 8, 0, offs, 12) == sky.E_INVAL
     vals = list(offs)
     assert vals == sorted(vals) and all(v % 256 == 0 for v in vals)
     assert vals[-1] == a

@@ -175,6 +175,17 @@ def test_deterministic_repeat(oracle_mod):
 
 
 # ---------------------------------------------------------------- intermediate steps
+def _morton(coords, g):
+    """Cell index of the library's documented layout: bit b of column k at b*d + k."""
+    n, d = coords.shape
+    r = int(np.ceil(np.log2(g))) if g > 1 else 0
+    idx = np.zeros(n, dtype=np.int64)
+    for b in range(r):
+        for k in range(d):
+            idx |= ((coords[:, k].astype(np.int64) >> b) & 1) << (b * d + k)
+    return idx
+
+
 def test_quantiser_and_cell_prune_intermediates(oracle_mod):
     """K1 cell ids bit-exact with the oracle's Equation 1, K3 surviving flags equal to
     brute-force Definition 3 over the non-empty cells."""
@@ -186,31 +197,30 @@ def test_quantiser_and_cell_prune_intermediates(oracle_mod):
         s = sky.Skyline(n, d, grid_res=g, device=dev)
         s.run(torch.from_numpy(np.ascontiguousarray(x.T)).to(dev))
         torch.cuda.synchronize()
-        offs = (ctypes.c_size_t * 12)()
-        assert sky.lib().skycell_workspace_layout(n, d, g, 0, offs, 12) == 0
+        offs = sky.workspace_layout(n, d, g)
+        r = int(np.ceil(np.log2(g)))
+        cells = 1 << (r * d)
         ws = s.workspace.cpu().numpy()
         cell_of = ws[offs[0]:offs[0] + 4 * n].view(np.uint32)
-        info = ws[offs[3]:offs[3] + 4 * g ** d].view(np.uint32)
+        rec = ws[offs[4]:offs[4] + 8 * cells].view(np.uint64)
         coords = oracle_mod.cell_coords(x, g)
-        ref_cell = (coords.astype(np.int64) * (g ** np.arange(d))).sum(axis=1)
-        assert np.array_equal(cell_of.astype(np.int64), ref_cell)
-        ne = np.unique(ref_cell)
-        ne_coords = np.stack([(ne // g ** k) % g for k in range(d)], axis=1).astype(np.int32)
+        assert np.array_equal(cell_of.astype(np.int64), _morton(coords, g))
+        ne_coords = np.unique(coords, axis=0).astype(np.int32)
         dom = oracle_mod.cells_dominated(ne_coords)
-        surv_gpu = (info >> 31).astype(bool)
-        expect = np.zeros(g ** d, dtype=bool)
-        expect[ne[~dom]] = True
+        expect = np.zeros(cells, dtype=bool)
+        expect[_morton(ne_coords[~dom], g)] = True
+        surv_gpu = (rec >> np.uint64(63)).astype(bool)
         assert np.array_equal(surv_gpu, expect)
         assert expect.sum() <= g ** d - (g - 1) ** d  # Equation 14 (E6 bound)
-    # the worked example of Equation 1
+    # the worked example of Equation 1: (dim1, dim0) = (0.63, 0.08)
     p = np.asarray([[0.08, 0.63]], dtype=np.float32)
-    for g, want in ((8, 0 + 5 * 8), (16, 1 + 10 * 16)):
+    for g, want in ((8, (0, 5)), (16, (1, 10))):
         s = sky.Skyline(1, 2, grid_res=g, device=dev)
         s.run(torch.from_numpy(np.ascontiguousarray(p.T)).to(dev))
         torch.cuda.synchronize()
-        offs = (ctypes.c_size_t * 12)()
-        sky.lib().skycell_workspace_layout(1, 2, g, 0, offs, 12)
-        assert int(s.workspace.cpu().numpy()[offs[0]:offs[0] + 4].view(np.uint32)[0]) == want
+        offs = sky.workspace_layout(1, 2, g)
+        got = int(s.workspace.cpu().numpy()[offs[0]:offs[0] + 4].view(np.uint32)[0])
+        assert got == int(_morton(np.asarray([want]), g)[0])
 
 
 # ---------------------------------------------------------------- larger configs
