@@ -1,0 +1,125 @@
+// Per-element operations of the grid phase, shared by the single-instance
+// kernels (one thread per element over the whole GPU) and the batched kernel
+// (one workgroup per instance).
+#pragma once
+
+#include "common.h"
+#include "../../include/skycell.h"
+
+namespace skycell {
+
+// Column of a binary32 value: floor of the binary32 product x*g (round to
+// nearest), clamped to [0, g-1].  Non-decreasing in x, which is all that cell
+// pruning needs to stay exact.
+__device__ __forceinline__ uint32_t column_f32(float v, float gf, uint32_t g, bool &nan)
+{
+    if (v != v) {
+        nan = true;
+        return 0u;
+    }
+    const float f = floorf(__fmul_rn(v, gf));
+    if (!(f >= 0.0f)) return 0u;
+    if (f >= gf) return g - 1u;
+    return (uint32_t)f;
+}
+
+__device__ __forceinline__ uint32_t column_u16(uint16_t v, uint32_t g, int bits)
+{
+    const uint64_t c = ((uint64_t)v * g) >> bits;
+    return c > g - 1u ? g - 1u : (uint32_t)c;
+}
+
+// Equation 1 for point i of an SoA block: Morton index of its cell.
+template <typename T>
+__device__ __forceinline__ uint32_t point_cell(const T *__restrict__ pts, uint32_t n, uint32_t i,
+                                               const GridDesc &gd, int value_bits, bool &nan)
+{
+    const float gf = (float)gd.g;
+    uint32_t cell = 0u;
+    for (int k = 0; k < gd.d; ++k) {
+        const T v = pts[(size_t)k * n + i];
+        uint32_t c;
+        if constexpr (sizeof(T) == 4)
+            c = column_f32(v, gf, (uint32_t)gd.g, nan);
+        else
+            c = column_u16(v, (uint32_t)gd.g, value_bits);
+        cell |= deposit_bits(c, gd.mask[k]);
+    }
+    return cell;
+}
+
+// Inclusive prefix-OR of the lower-closure flags along one line of cells that
+// differ only in the dimension whose index bits are `m` (line t of all_bits >> r).
+__device__ __forceinline__ void lc_prefix_line(uint8_t *__restrict__ lc, uint32_t t, uint32_t m,
+                                               uint32_t all_bits, uint32_t g)
+{
+    uint32_t x = deposit_bits(t, all_bits & ~m);
+    uint8_t v = 0;
+    for (uint32_t j = 0; j < g; ++j) {
+        v |= lc[x];
+        lc[x] = v;
+        if (j + 1 < g) x = morton_inc(x, m);
+    }
+}
+
+// Cell record without its start (see common.h):
+//   dominated(x)  iff  every column of x is >= 1 and lc[x - (1,...,1)] = 1,
+//   i.e. a non-empty cell has a smaller column in every dimension (Definition 3);
+//   mask bit k    iff  column k of x is >= 1 and lc[x - e_k] = 1, i.e. the cone
+//                      below x - e_k still holds a non-empty cell.
+__device__ __forceinline__ uint64_t cell_record(const GridDesc &gd, const uint32_t *__restrict__ cnt,
+                                                const uint8_t *__restrict__ lc, uint32_t x,
+                                                bool &occ, bool &surv)
+{
+    uint32_t nbr = 0u, diag = x;
+    bool all_pos = true;
+    for (int k = 0; k < gd.d; ++k) {
+        const uint32_t m = gd.mask[k];
+        if ((x & m) == 0u) {
+            all_pos = false;
+        } else {
+            if (lc[morton_dec(x, m)]) nbr |= 1u << k;
+            diag = morton_dec(diag, m);
+        }
+    }
+    const uint32_t c = cnt[x];
+    occ = c != 0u;
+    surv = occ && !(all_pos && lc[diag]);
+    const uint64_t cs = surv ? (c < kRecCountSat ? c : kRecCountSat) : 0u;
+    return ((uint64_t)(surv ? 1u : 0u) << 63) | ((uint64_t)nbr << 47) | (cs << 32);
+}
+
+// Scatter of point i of a surviving cell to sorted position pos: exact
+// order-preserving keys and packed screening columns.
+template <typename T>
+__device__ __forceinline__ void scatter_point(const T *__restrict__ pts, uint32_t n, int d,
+                                              int value_bits, uint32_t i, uint32_t pos,
+                                              uint32_t *__restrict__ keys,
+                                              uint64_t *__restrict__ fkeys,
+                                              int32_t *__restrict__ sidx)
+{
+    uint32_t *dst = keys + (size_t)pos * d;
+    const int fw = fine_words(d);
+    uint64_t *fdst = fkeys + (size_t)pos * fw;
+    uint64_t word = 0ull;
+    bool nan = false;
+    for (int k = 0; k < d; ++k) {
+        const T v = pts[(size_t)k * n + i];
+        uint32_t f;
+        if constexpr (sizeof(T) == 4) {
+            dst[k] = f32_key(v);
+            f = column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan);
+        } else {
+            dst[k] = (uint32_t)v;
+            f = column_u16(v, (uint32_t)kFineCols, value_bits);
+        }
+        word |= (uint64_t)f << (8 * (k & 7));
+        if ((k & 7) == 7 || k == d - 1) {
+            fdst[k >> 3] = word;
+            word = 0ull;
+        }
+    }
+    sidx[pos] = (int32_t)i;
+}
+
+}  // namespace skycell

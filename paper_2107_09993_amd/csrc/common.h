@@ -34,7 +34,7 @@ __host__ __device__ __forceinline__ bool rec_surv(uint64_t r) { return (r >> 63)
 constexpr int kFineCols = 128;
 __host__ __device__ constexpr int fine_words(int d) { return (d + 7) / 8; }
 
-// Query points per refine work item, by dimensionality.
+// Default number of query points per refine work item, by dimensionality.
 __host__ __device__ constexpr int items_per_group(int d) { return d <= 8 ? 4 : 2; }
 
 // Number of XCDs (each with its own L2) that workgroups are spread over
@@ -53,6 +53,7 @@ struct GridDesc {
     int32_t r;                 // index bits per dimension
     uint32_t cells;            // 2^(r*d): size of the index space
     uint32_t mask[kMaxD];      // index bits that hold dimension k
+    int32_t m;                 // query points per refine work item (1, 2 or 4)
 };
 
 // Index of the cell one column lower / higher in the dimension whose bits are

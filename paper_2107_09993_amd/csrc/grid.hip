@@ -8,6 +8,7 @@
 //   K2  exclusive scan of surviving-cell counts: counting-sort offsets and refine
 //       work items;
 //   K4  scatter of surviving points, grouped by cell, as order-preserving keys.
+#include "cellops.h"
 #include "common.h"
 #include "scan.h"
 #include "../../include/skycell.h"
@@ -45,27 +46,6 @@ hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats,
 }
 
 // ------------------------------------------------------------------ K1
-// Column of a binary32 value: floor of the binary32 product x*g (round to
-// nearest), clamped to [0, g-1].  Non-decreasing in x, which is all that cell
-// pruning needs to stay exact.
-__device__ __forceinline__ uint32_t column_f32(float v, float gf, uint32_t g, bool &nan)
-{
-    if (v != v) {
-        nan = true;
-        return 0u;
-    }
-    const float f = floorf(__fmul_rn(v, gf));
-    if (!(f >= 0.0f)) return 0u;
-    if (f >= gf) return g - 1u;
-    return (uint32_t)f;
-}
-
-__device__ __forceinline__ uint32_t column_u16(uint16_t v, uint32_t g, int bits)
-{
-    const uint64_t c = ((uint64_t)v * g) >> bits;
-    return c > g - 1u ? g - 1u : (uint32_t)c;
-}
-
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict__ pts, uint32_t n,
                                                             GridDesc gd, int value_bits,
@@ -76,18 +56,8 @@ __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict_
 {
     const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    const float gf = (float)gd.g;
-    uint32_t cell = 0u;
     bool nan = false;
-    for (int k = 0; k < gd.d; ++k) {
-        const T v = pts[(size_t)k * n + i];
-        uint32_t c;
-        if constexpr (sizeof(T) == 4)
-            c = column_f32(v, gf, (uint32_t)gd.g, nan);
-        else
-            c = column_u16(v, (uint32_t)gd.g, value_bits);
-        cell |= deposit_bits(c, gd.mask[k]);
-    }
+    const uint32_t cell = point_cell(pts, n, i, gd, value_bits, nan);
     cell_of[i] = cell;
     rank[i] = atomicAdd(&cnt[cell], 1u);
     if (nan) atomicOr(&ctr[kCtrErr], 1u);
@@ -123,23 +93,11 @@ __global__ __launch_bounds__(kThreads) void k_lc_prefix(uint8_t *__restrict__ lc
                                                         uint32_t m, uint32_t all_bits, uint32_t g)
 {
     const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= lines) return;
-    uint32_t x = deposit_bits(t, all_bits & ~m);
-    uint8_t v = 0;
-    for (uint32_t j = 0; j < g; ++j) {
-        v |= lc[x];
-        lc[x] = v;
-        if (j + 1 < g) x = morton_inc(x, m);
-    }
+    if (t < lines) lc_prefix_line(lc, t, m, all_bits, g);
 }
 
-// Per cell: the surviving flag, the lower-neighbour mask and the (saturated)
-// point count, written as the high half of the cell record; the scan fills in
-// the low half (first sorted position).
-//   dominated(x)  iff  every column of x is >= 1 and lc[x - (1,...,1)] = 1,
-//   i.e. a non-empty cell has a smaller column in every dimension (Definition 3).
-//   mask bit k    iff  column k of x is >= 1 and lc[x - e_k] = 1, i.e. the cone
-//                      below x - e_k still holds a non-empty cell.
+// Per cell: the high half of the cell record (see cellops.h); the scan fills
+// in the low half (first sorted position).
 __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32_t *__restrict__ cnt,
                                                        const uint8_t *__restrict__ lc,
                                                        uint64_t *__restrict__ rec,
@@ -147,24 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32
 {
     const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
     bool occ = false, surv = false;
-    if (x < gd.cells) {
-        uint32_t nbr = 0u, diag = x;
-        bool all_pos = true;
-        for (int k = 0; k < gd.d; ++k) {
-            const uint32_t m = gd.mask[k];
-            if ((x & m) == 0u) {
-                all_pos = false;
-            } else {
-                if (lc[morton_dec(x, m)]) nbr |= 1u << k;
-                diag = morton_dec(diag, m);
-            }
-        }
-        const uint32_t c = cnt[x];
-        occ = c != 0u;
-        surv = occ && !(all_pos && lc[diag]);
-        const uint64_t cs = surv ? (c < kRecCountSat ? c : kRecCountSat) : 0u;
-        rec[x] = ((uint64_t)(surv ? 1u : 0u) << 63) | ((uint64_t)nbr << 47) | (cs << 32);
-    }
+    if (x < gd.cells) rec[x] = cell_record(gd, cnt, lc, x, occ, surv);
     if (stats != nullptr) {
         const uint64_t bo = __ballot(occ), bs = __ballot(surv);
         if (__lane_id() == 0) {
@@ -242,7 +183,7 @@ __global__ void k_cell_scan_total(const uint64_t *block_sums, uint32_t nb, uint3
 
 hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st)
 {
-    const uint32_t m = (uint32_t)items_per_group(gd.d);
+    const uint32_t m = (uint32_t)gd.m;
     CellLoader ld{ws.rec, ws.cnt, m};
     CellEmitter em{(uint32_t *)ws.rec, ws.items, m};
     hipError_t e = enqueue_scan<uint64_t>(ld, em, gd.cells, ws.block_sums, st);
@@ -275,29 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts,
     const uint32_t x = cell_of[i];
     const uint64_t r = rec[x];
     if (!rec_surv(r)) return;
-    const uint32_t pos = rec_start(r) + rank[i];
-    uint32_t *dst = keys + (size_t)pos * d;
-    const int fw = fine_words(d);
-    uint64_t *fdst = fkeys + (size_t)pos * fw;
-    uint64_t word = 0ull;
-    bool nan = false;
-    for (int k = 0; k < d; ++k) {
-        const T v = pts[(size_t)k * n + i];
-        uint32_t f;
-        if constexpr (sizeof(T) == 4) {
-            dst[k] = f32_key(v);
-            f = column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan);
-        } else {
-            dst[k] = (uint32_t)v;
-            f = column_u16(v, (uint32_t)kFineCols, value_bits);
-        }
-        word |= (uint64_t)f << (8 * (k & 7));
-        if ((k & 7) == 7 || k == d - 1) {
-            fdst[k >> 3] = word;
-            word = 0ull;
-        }
-    }
-    sidx[pos] = (int32_t)i;
+    scatter_point(pts, n, d, value_bits, i, rec_start(r) + rank[i], keys, fkeys, sidx);
 }
 
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -93,12 +94,26 @@ static int choose_grid(int64_t n, int d, int dtype)
     return default_grid(n, d);
 }
 
+// Query points per refine work item: the default for d, or SKYCELL_ITEMS_PER_LANE
+// (1, 2 or 4) when set, for tuning sweeps.
+static int items_per_lane(int d)
+{
+    static int env = -1;
+    if (env < 0) {
+        const char *v = getenv("SKYCELL_ITEMS_PER_LANE");
+        const int e = v ? atoi(v) : 0;
+        env = (e == 1 || e == 2 || e == 4) ? e : 0;
+    }
+    return env > 0 ? env : items_per_group(d);
+}
+
 static GridDesc make_grid(int d, int g)
 {
     GridDesc gd;
     memset(&gd, 0, sizeof(gd));
     gd.d = d;
     gd.g = g;
+    gd.m = items_per_lane(d);
     gd.r = index_bits(g);
     gd.cells = 1u << (gd.r * d);
     for (int k = 0; k < d; ++k)
