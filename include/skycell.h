@@ -168,6 +168,50 @@ int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dty
 int skycell_profile_enable(int32_t on);
 int skycell_profile_read(float *ms, int32_t count);
 
+/*
+ * Batched skylines: many independent instances of uneven n and d computed by
+ * one persistent kernel launch, captured once into a hipGraph at plan
+ * creation.  Every instance's result equals skycell_compute on its own points.
+ *
+ *   num_inst   number of instances, >= 1.
+ *   n, d       host arrays [num_inst]: points and attributes of each instance
+ *              (0 <= n < 2^31, total points below 2^31, 1 <= d <= 16).
+ *   dtype      SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16 (value_bits as in
+ *              skycell_compute_u16; ignored for F32).
+ *   grid_res   host array [num_inst] of cells per dimension (0 entries, or a
+ *              NULL array, let the autotuner choose per instance); each grid's
+ *              index space is limited to 2^20 cells.
+ *   plan       receives an opaque handle owning the device workspace and the
+ *              graph.  Creating a plan allocates device memory and synchronises
+ *              the device; it is not capture-safe.
+ *
+ * Buffers of a run (device memory, caller-owned):
+ *   points     instance b occupies elements [P_b, P_{b+1}) as an SoA block
+ *              [d_b][n_b] (attribute k of point i at P_b + k*n_b + i), with
+ *              P_b = sum_{a<b} n_a * d_a (skycell_batched_offsets gives P).
+ *   out_idx    int32 [sum n]: instance b's skyline indices (local, 0..n_b-1,
+ *              ascending) start at O_b = sum_{a<b} n_a.
+ *   out_count  int32 [num_inst]: skyline size of each instance, or
+ *              SKYCELL_E_NAN if the instance holds a NaN.
+ * A run is one hipGraphLaunch on `stream`.  Runs of one plan must not overlap
+ * in time (they share the plan's workspace and control words).
+ */
+typedef struct skycell_plan *skycell_plan_t;
+
+int skycell_batched_plan_create(int32_t num_inst, const int64_t *n, const int32_t *d, int32_t dtype,
+                                int32_t value_bits, const int32_t *grid_res, skycell_plan_t *plan);
+
+/* Host arrays [num_inst + 1] of element offsets P_b and output offsets O_b, and
+ * [num_inst] of the grid chosen per instance; any pointer may be NULL. */
+int skycell_batched_offsets(skycell_plan_t plan, int64_t *points_off, int64_t *out_off,
+                            int32_t *grid_res);
+
+int skycell_batched_run(skycell_plan_t plan, const void *points, int32_t *out_idx,
+                        int32_t *out_count, void *stream);
+
+/* Waits for the device, then frees the plan's memory and graph. */
+int skycell_plan_destroy(skycell_plan_t plan);
+
 /* Text for the last nonzero return of the calling thread ("" if none). */
 const char *skycell_last_error(void);
 

@@ -57,11 +57,17 @@ def lib():
     L.skycell_workspace_layout.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz), i32]
     L.skycell_profile_enable.argtypes = [i32]
     L.skycell_profile_read.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
+    L.skycell_batched_plan_create.argtypes = [i32, p, p, i32, i32, p, ctypes.POINTER(p)]
+    L.skycell_batched_offsets.argtypes = [p, p, p, p]
+    L.skycell_batched_run.argtypes = [p, p, p, p, p]
+    L.skycell_plan_destroy.argtypes = [p]
     L.skycell_last_error.argtypes = []
     L.skycell_last_error.restype = ctypes.c_char_p
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
                  "skycell_compute_ws", "skycell_choose_grid", "skycell_load_tuning",
-                 "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read"):
+                 "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
+                 "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
+                 "skycell_plan_destroy"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -196,3 +202,81 @@ def compute(points, grid_res=0, layout="nd", value_bits=10, return_stats=False):
     if return_stats:
         return out, sk.stats_dict()
     return out
+
+
+class BatchedPlan:
+    """Many independent skylines in one persistent, graph-captured launch.
+
+    ns, ds: per-instance point counts and dimensionalities.  The points of all
+    instances live in one device buffer of concatenated SoA blocks (see
+    ``pack``); results come back per instance as local ascending indices.
+    """
+
+    def __init__(self, ns, ds, dtype="f32", value_bits=10, grid_res=None, device="cuda"):
+        import numpy as np
+        import torch
+        self.num = len(ns)
+        if len(ds) != self.num:
+            raise ValueError("ns and ds differ in length")
+        self.ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+        self.ds = np.ascontiguousarray(np.asarray(ds, dtype=np.int32))
+        self.dtype = DTYPE_F32 if dtype in ("f32", DTYPE_F32) else DTYPE_U16
+        self.device = torch.device(device)
+        g = None if grid_res is None else np.ascontiguousarray(np.asarray(grid_res, dtype=np.int32))
+        handle = ctypes.c_void_p()
+        _check(lib().skycell_batched_plan_create(
+            self.num, self.ns.ctypes.data, self.ds.ctypes.data, self.dtype, int(value_bits),
+            g.ctypes.data if g is not None else None, ctypes.byref(handle)))
+        self.handle = handle
+        self.points_off = np.zeros(self.num + 1, dtype=np.int64)
+        self.out_off = np.zeros(self.num + 1, dtype=np.int64)
+        self.grid_res = np.zeros(self.num, dtype=np.int32)
+        _check(lib().skycell_batched_offsets(self.handle, self.points_off.ctypes.data,
+                                             self.out_off.ctypes.data, self.grid_res.ctypes.data))
+        self.out_idx = torch.empty(max(int(self.out_off[-1]), 1), dtype=torch.int32, device=self.device)
+        self.out_count = torch.empty(self.num, dtype=torch.int32, device=self.device)
+
+    def pack(self, arrays):
+        """Host arrays [n_b, d_b] -> one device buffer of SoA blocks."""
+        import numpy as np
+        import torch
+        tdt = np.float32 if self.dtype == DTYPE_F32 else np.uint16
+        buf = np.empty(max(int(self.points_off[-1]), 1), dtype=tdt)
+        for b, a in enumerate(arrays):
+            a = np.asarray(a)
+            if a.shape != (int(self.ns[b]), int(self.ds[b])) or a.dtype != tdt:
+                raise ValueError("instance %d: expected %s array of shape (%d, %d)" %
+                                 (b, tdt.__name__, self.ns[b], self.ds[b]))
+            buf[self.points_off[b]:self.points_off[b + 1]] = a.T.reshape(-1)
+        return torch.from_numpy(buf).to(self.device)
+
+    def run(self, points, stream=None):
+        """Enqueue one batched launch over `points` (a packed device buffer)."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().skycell_batched_run(self.handle, ctypes.c_void_p(points.data_ptr()),
+                                         ctypes.c_void_p(self.out_idx.data_ptr()),
+                                         ctypes.c_void_p(self.out_count.data_ptr()), ctypes.c_void_p(st)))
+
+    def results(self):
+        """Per-instance skyline indices (numpy int32), after synchronising."""
+        counts = self.out_count.cpu().numpy()
+        idx = self.out_idx.cpu().numpy()
+        out = []
+        for b in range(self.num):
+            c = int(counts[b])
+            if c < 0:
+                raise SkycellError(c, "instance %d: device reported %s" % (b, "NaN" if c == E_NAN else "error"))
+            out.append(idx[self.out_off[b]:self.out_off[b] + c].copy())
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().skycell_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -133,41 +133,6 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *
 }
 
 // ------------------------------------------------------------------ K2
-// Scan value per cell: surviving points (low 32 bits) and refine work items
-// (high 32 bits); a cell with m surviving points gives ceil(m / M) items.
-struct CellLoader {
-    const uint64_t *rec;
-    const uint32_t *cnt;
-    uint32_t per_item;
-    __device__ uint64_t operator()(uint64_t x) const
-    {
-        const uint32_t m = rec_surv(rec[x]) ? cnt[x] : 0u;
-        const uint32_t it = (m + per_item - 1u) / per_item;
-        return (uint64_t)m | ((uint64_t)it << 32);
-    }
-};
-
-// Writes the first sorted position into the low half of the cell record and
-// the cell's work items: (first sorted position, (point count << 26) | cell).
-struct CellEmitter {
-    uint32_t *rec_words;
-    uint2 *items;
-    uint32_t per_item;
-    __device__ void operator()(uint64_t x, uint64_t prefix, uint64_t v) const
-    {
-        const uint32_t start = (uint32_t)prefix;
-        rec_words[2 * x] = start;
-        const uint32_t m = (uint32_t)v;
-        const uint32_t it = (uint32_t)(v >> 32);
-        const uint32_t ibase = (uint32_t)(prefix >> 32);
-        for (uint32_t t = 0; t < it; ++t) {
-            const uint32_t first = t * per_item;
-            const uint32_t c = (m - first) < per_item ? (m - first) : per_item;
-            items[ibase + t] = make_uint2(start + first, (c << 26) | (uint32_t)x);
-        }
-    }
-};
-
 __global__ void k_cell_scan_total(const uint64_t *block_sums, uint32_t nb, uint32_t cells,
                                   uint64_t *rec, uint32_t *ctr, uint64_t *stats)
 {

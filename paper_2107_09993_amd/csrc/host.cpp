@@ -16,12 +16,13 @@
 #include "../../include/skycell.h"
 #include "common.h"
 #include "scan.h"
+#include "host_internal.h"
 
 namespace skycell {
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char *fmt, ...)
+int set_error(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -32,11 +33,14 @@ static int fail(int code, const char *fmt, ...)
     return code;
 }
 
-static int ok()
+int clear_error()
 {
     g_last_error.clear();
     return SKYCELL_OK;
 }
+
+#define fail set_error
+#define ok clear_error
 
 // ---------------------------------------------------------------- grid choice
 struct TuneEntry {
@@ -57,7 +61,7 @@ static int index_bits(int g)
 }
 
 // Size of the Morton index space, 2^(r*d), saturated above the cell budget.
-static uint64_t cells_of(int g, int d)
+uint64_t grid_cells(int g, int d)
 {
     const int r = index_bits(g);
     if ((uint64_t)r * (uint64_t)d > 26) return (uint64_t)kMaxCells + 1;
@@ -73,7 +77,33 @@ static int default_grid(int64_t n, int d)
     if (target < 4096.0) target = 4096.0;
     if (target > (double)(1u << 24)) target = (double)(1u << 24);
     int g = 1;
-    while (cells_of(g + 1, d) <= (uint64_t)target) ++g;
+    while (grid_cells(g + 1, d) <= (uint64_t)target) ++g;
+    return g;
+}
+
+// Batched instances: the tuning table entry for (d, n) under dtype code
+// dtype + 2, else about two cells per point within 2^20 cells.
+int choose_grid_batched(int64_t n, int d, int dtype)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        int best = -1, best_dist = 1 << 30;
+        const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
+        for (const TuneEntry &e : g_tune) {
+            if (e.d != d || e.dtype != dtype + 2) continue;
+            const int dist = std::abs(e.log2n - l2);
+            if (dist < best_dist) {
+                best_dist = dist;
+                best = e.g;
+            }
+        }
+        if (best >= 1 && grid_cells(best, d) <= (1u << 20)) return best;
+    }
+    double target = 2.0 * (double)n;
+    if (target < 256.0) target = 256.0;
+    if (target > (double)(1u << 20)) target = (double)(1u << 20);
+    int g = 1;
+    while (grid_cells(g + 1, d) <= (uint64_t)target) ++g;
     return g;
 }
 
@@ -90,7 +120,7 @@ static int choose_grid(int64_t n, int d, int dtype)
             best = e.g;
         }
     }
-    if (best >= 1 && cells_of(best, d) <= kMaxCells) return best;
+    if (best >= 1 && grid_cells(best, d) <= kMaxCells) return best;
     return default_grid(n, d);
 }
 
@@ -107,7 +137,7 @@ static int items_per_lane(int d)
     return env > 0 ? env : items_per_group(d);
 }
 
-static GridDesc make_grid(int d, int g)
+GridDesc grid_desc(int d, int g)
 {
     GridDesc gd;
     memset(&gd, 0, sizeof(gd));
@@ -155,7 +185,7 @@ size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *b
 static std::mutex g_dev_mu;
 static std::map<int, int> g_num_cus;
 
-static int device_cus(int dev)
+int device_cus(int dev)
 {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     auto it = g_num_cus.find(dev);
@@ -197,7 +227,7 @@ static int validate(const void *points, int32_t dtype, int64_t n, int32_t d, int
 static int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out)
 {
     const int g = grid_res > 0 ? grid_res : choose_grid(n, d, dtype);
-    if (cells_of(g, d) > kMaxCells)
+    if (grid_cells(g, d) > kMaxCells)
         return fail(SKYCELL_E_RANGE,
                     "grid of %d columns in %d dimensions needs 2^(%d*%d) cells, over the budget of %u",
                     g, d, index_bits(g), d, (unsigned)kMaxCells);
@@ -255,7 +285,7 @@ static int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d,
                         int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
                         uint64_t *stats, hipStream_t st)
 {
-    const GridDesc gd = make_grid(d, g);
+    const GridDesc gd = grid_desc(d, g);
     Workspace ws;
     workspace_layout(n, d, gd.cells, &ws, (char *)workspace);
     int dev = 0;
@@ -290,7 +320,7 @@ static int compute_owned(const void *points, int32_t dtype, int64_t n, int32_t d
         SKYCELL_HIP_CHECK(launch_write_zero_count(out_count, st));
         return ok();
     }
-    const size_t need = workspace_layout(n, d, make_grid(d, g).cells, nullptr, nullptr);
+    const size_t need = workspace_layout(n, d, grid_desc(d, g).cells, nullptr, nullptr);
     int dev = 0;
     SKYCELL_HIP_CHECK(hipGetDevice(&dev));
     void *ptr = nullptr;
@@ -345,7 +375,7 @@ int skycell_workspace_bytes(int64_t n, int32_t d, int32_t grid_res, int32_t dtyp
     int g = 0;
     int rc = resolve_grid(n, d, dtype, grid_res, &g);
     if (rc != SKYCELL_OK) return rc;
-    *bytes = n == 0 ? 256 : workspace_layout(n, d, make_grid(d, g).cells, nullptr, nullptr);
+    *bytes = n == 0 ? 256 : workspace_layout(n, d, grid_desc(d, g).cells, nullptr, nullptr);
     return ok();
 }
 
@@ -363,7 +393,7 @@ int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d, 
         SKYCELL_HIP_CHECK(launch_write_zero_count(out_count, st));
         return ok();
     }
-    const size_t need = workspace_layout(n, d, make_grid(d, g).cells, nullptr, nullptr);
+    const size_t need = workspace_layout(n, d, grid_desc(d, g).cells, nullptr, nullptr);
     if (workspace == nullptr || ws_bytes < need)
         return fail(SKYCELL_E_NOMEM, "workspace of %zu bytes is smaller than the %zu required",
                     workspace ? ws_bytes : (size_t)0, need);
@@ -416,7 +446,7 @@ int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dty
     if (rc != SKYCELL_OK) return rc;
     Workspace w;
     char *const base = (char *)(uintptr_t)4096;  // any aligned base; offsets are relative
-    const size_t total = workspace_layout(n, d, make_grid(d, g).cells, &w, base);
+    const size_t total = workspace_layout(n, d, grid_desc(d, g).cells, &w, base);
     const void *ptrs[12] = {w.cell_of, w.rank, w.cnt, w.lc, w.rec, w.keys, w.fkeys, w.sidx, w.items,
                             w.flag, w.block_sums, w.ctr};
     for (int i = 0; i < 12; ++i) offsets[i] = (size_t)((const char *)ptrs[i] - base);

@@ -122,3 +122,23 @@ def test_tuning_table_roundtrip(tmp_path):
     finally:
         sky.load_tuning(None)
     assert sky.choose_grid(1 << 20, 8) != 4 or True
+
+
+def test_batched_plan_argument_errors():
+    import numpy as np
+    lib = sky.lib()
+    h = ctypes.c_void_p()
+    n = np.asarray([10, 20], dtype=np.int64)
+    d = np.asarray([3, 4], dtype=np.int32)
+    assert lib.skycell_batched_plan_create(0, n.ctypes.data, d.ctypes.data, 0, 16, None, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_batched_plan_create(2, None, d.ctypes.data, 0, 16, None, ctypes.byref(h)) == sky.E_INVAL
+    bad_d = np.asarray([3, 17], dtype=np.int32)
+    assert lib.skycell_batched_plan_create(2, n.ctypes.data, bad_d.ctypes.data, 0, 16, None, ctypes.byref(h)) == sky.E_INVAL
+    bad_n = np.asarray([10, -1], dtype=np.int64)
+    assert lib.skycell_batched_plan_create(2, bad_n.ctypes.data, d.ctypes.data, 0, 16, None, ctypes.byref(h)) == sky.E_INVAL
+    g = np.asarray([8, 64], dtype=np.int32)  # 64^4 = 2^24 cells > 2^20 per instance
+    assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 0, 16, g.ctypes.data, ctypes.byref(h)) == sky.E_RANGE
+    assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 1, 0, None, ctypes.byref(h)) == sky.E_RANGE
+    assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 5, 16, None, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_batched_run(None, FAKE, FAKE, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_plan_destroy(None) == sky.E_INVAL
