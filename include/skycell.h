@@ -193,8 +193,11 @@ int skycell_profile_read(float *ms, int32_t count);
  *              ascending) start at O_b = sum_{a<b} n_a.
  *   out_count  int32 [num_inst]: skyline size of each instance, or
  *              SKYCELL_E_NAN if the instance holds a NaN.
- * A run is one hipGraphLaunch on `stream`.  Runs of one plan must not overlap
- * in time (they share the plan's workspace and control words).
+ * A run is one hipGraphLaunch on `stream`.  The graph is captured with the
+ * run's buffers at the first run and again whenever a run passes different
+ * buffers (capturing costs about a kernel launch; pass the same buffers to
+ * replay it).  Runs of one plan must not overlap in time (they share the
+ * plan's workspace and control words).
  */
 typedef struct skycell_plan *skycell_plan_t;
 

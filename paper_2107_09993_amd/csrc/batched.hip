@@ -1,5 +1,5 @@
 // Batched skyline: many independent instances of uneven n and d in one
-// persistent launch (captured once into a hipGraph by the plan).
+// persistent launch (captured into a hipGraph by the plan).
 //
 // Stage A (one workgroup per instance): a workgroup claims the next instance
 // in the plan's order (largest estimated work first), runs every grid phase

@@ -35,7 +35,6 @@ struct skycell_plan {
     size_t ws_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t node = nullptr;
     const void *bound_points = nullptr;
     int32_t *bound_out_idx = nullptr;
     int32_t *bound_out_count = nullptr;
@@ -57,10 +56,25 @@ void plan_free(skycell_plan *p)
     delete p;
 }
 
-// Bind the buffers of this run to the captured kernel node.
-hipError_t bind(skycell_plan *p, const void *points, int32_t *out_idx, int32_t *out_count)
+void drop_graph(skycell_plan *p)
 {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->bound_points = nullptr;
+    p->bound_out_idx = nullptr;
+    p->bound_out_count = nullptr;
+}
+
+// Capture the persistent launch with this run's buffers as its arguments into
+// a one-node graph and instantiate it.  The graph is kept and replayed while
+// later runs pass the same buffers.
+hipError_t capture(skycell_plan *p, const void *points, int32_t *out_idx, int32_t *out_count)
+{
+    drop_graph(p);
     BatchLaunch L;
+    memset(&L, 0, sizeof(L));
     L.dtype = p->dtype;
     L.points = points;
     L.inst = p->d_inst;
@@ -75,24 +89,25 @@ hipError_t bind(skycell_plan *p, const void *points, int32_t *out_idx, int32_t *
     L.out_count = out_count;
     L.value_bits = p->value_bits;
     L.blocks = p->blocks;
-    void *args[] = {(void *)&L.points, (void *)&L.inst, (void *)&L.prep_order, (void *)&L.num_inst,
-                    (void *)&L.chunk_inst, (void *)&L.num_chunks, (void *)&L.chunk_items, (void *)&L.ctl,
-                    (void *)&L.ictl, (void *)&L.out_idx, (void *)&L.out_count, (void *)&L.value_bits};
-    hipKernelNodeParams kp;
-    memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void *>(batched_kernel(p->dtype));
-    kp.gridDim = dim3(p->blocks);
-    kp.blockDim = dim3((unsigned)batched_threads());
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = args;
-    kp.extra = nullptr;
-    hipError_t e = hipGraphExecKernelNodeSetParams(p->exec, p->node, &kp);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        p->bound_points = points;
-        p->bound_out_idx = out_idx;
-        p->bound_out_count = out_count;
+        const hipError_t le = launch_batched(L, cs);
+        e = hipStreamEndCapture(cs, &p->graph);
+        if (e == hipSuccess) e = le;
     }
-    return e;
+    (void)hipStreamDestroy(cs);
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(p);
+        return e;
+    }
+    p->bound_points = points;
+    p->bound_out_idx = out_idx;
+    p->bound_out_count = out_count;
+    return hipSuccess;
 }
 
 }  // namespace
@@ -112,7 +127,7 @@ int skycell_batched_plan_create(int32_t num_inst, const int64_t *h_n, const int3
     if (value_bits < 1 || value_bits > 16) return set_error(SKYCELL_E_RANGE, "value_bits = %d outside [1, 16]", value_bits);
 
     std::vector<int> g(num_inst);
-    int64_t total_pts = 0, total_out = 0;
+    int64_t total_out = 0;
     for (int32_t b = 0; b < num_inst; ++b) {
         if (h_n[b] < 0 || h_n[b] >= ((int64_t)1 << 31))
             return set_error(SKYCELL_E_INVAL, "instance %d: n = %lld out of range", b, (long long)h_n[b]);
@@ -123,7 +138,6 @@ int skycell_batched_plan_create(int32_t num_inst, const int64_t *h_n, const int3
         if (grid_cells(g[b], h_d[b]) > kBatchMaxCells)
             return set_error(SKYCELL_E_RANGE, "instance %d: %d columns in %d dimensions exceed %u cells", b, g[b],
                              h_d[b], kBatchMaxCells);
-        total_pts += h_n[b] * h_d[b];
         total_out += h_n[b];
     }
     if (total_out >= ((int64_t)1 << 31)) return set_error(SKYCELL_E_RANGE, "batch holds 2^31 points or more");
@@ -207,36 +221,6 @@ int skycell_batched_plan_create(int32_t num_inst, const int64_t *h_n, const int3
 
     p->blocks = (unsigned)(device_cus(p->device) * batched_blocks_per_cu(dtype));
 
-    // capture the persistent launch once; each run rebinds its buffers
-    hipStream_t cs = nullptr;
-    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
-        return fail_free(SKYCELL_E_HIP, "capture stream", e);
-    BatchLaunch L;
-    memset(&L, 0, sizeof(L));
-    L.dtype = dtype;
-    L.inst = p->d_inst;
-    L.prep_order = p->d_prep_order;
-    L.num_inst = p->num_inst;
-    L.chunk_inst = p->d_chunk_inst;
-    L.num_chunks = p->num_chunks;
-    L.chunk_items = p->chunk_items;
-    L.ctl = p->d_ctl;
-    L.ictl = p->d_ictl;
-    L.value_bits = value_bits;
-    L.blocks = p->blocks;
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        const hipError_t le = launch_batched(L, cs);
-        e = hipStreamEndCapture(cs, &p->graph);
-        if (e == hipSuccess) e = le;
-    }
-    (void)hipStreamDestroy(cs);
-    if (e != hipSuccess) return fail_free(SKYCELL_E_HIP, "graph capture", e);
-    size_t nn = 1;
-    if ((e = hipGraphGetNodes(p->graph, &p->node, &nn)) != hipSuccess || nn != 1)
-        return fail_free(SKYCELL_E_HIP, "graph node", e == hipSuccess ? hipErrorInvalidValue : e);
-    if ((e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0)) != hipSuccess)
-        return fail_free(SKYCELL_E_HIP, "graph instantiation", e);
     *plan = p;
     return clear_error();
 }
@@ -263,9 +247,10 @@ int skycell_batched_run(skycell_plan_t plan, const void *points, int32_t *out_id
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return set_error(SKYCELL_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
     if (dev != plan->device) return set_error(SKYCELL_E_INVAL, "plan was created on device %d, current is %d", plan->device, dev);
-    if (points != plan->bound_points || out_idx != plan->bound_out_idx || out_count != plan->bound_out_count) {
-        if ((e = bind(plan, points, out_idx, out_count)) != hipSuccess)
-            return set_error(SKYCELL_E_HIP, "rebinding the graph: %s", hipGetErrorString(e));
+    if (plan->exec == nullptr || points != plan->bound_points || out_idx != plan->bound_out_idx ||
+        out_count != plan->bound_out_count) {
+        if ((e = capture(plan, points, out_idx, out_count)) != hipSuccess)
+            return set_error(SKYCELL_E_HIP, "capturing the batched launch: %s", hipGetErrorString(e));
     }
     if ((e = hipGraphLaunch(plan->exec, (hipStream_t)stream)) != hipSuccess)
         return set_error(SKYCELL_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
