@@ -170,8 +170,11 @@ int skycell_profile_read(float *ms, int32_t count);
 
 /*
  * Batched skylines: many independent instances of uneven n and d computed by
- * one persistent kernel launch, captured once into a hipGraph at plan
- * creation.  Every instance's result equals skycell_compute on its own points.
+ * one hipGraphLaunch.  The plan lays out every instance's workspace in one
+ * allocation; at the first run (and again when a run passes other buffers) it
+ * captures the single-instance path of every instance into one graph, spread
+ * over parallel branches, largest instances first.  Every instance's result
+ * equals skycell_compute on its own points.
  *
  *   num_inst   number of instances, >= 1.
  *   n, d       host arrays [num_inst]: points and attributes of each instance
@@ -182,8 +185,8 @@ int skycell_profile_read(float *ms, int32_t count);
  *              NULL array, let the autotuner choose per instance); each grid's
  *              index space is limited to 2^20 cells.
  *   plan       receives an opaque handle owning the device workspace and the
- *              graph.  Creating a plan allocates device memory and synchronises
- *              the device; it is not capture-safe.
+ *              graph.  Creating a plan allocates device memory; it is not
+ *              capture-safe.
  *
  * Buffers of a run (device memory, caller-owned):
  *   points     instance b occupies elements [P_b, P_{b+1}) as an SoA block
@@ -193,11 +196,10 @@ int skycell_profile_read(float *ms, int32_t count);
  *              ascending) start at O_b = sum_{a<b} n_a.
  *   out_count  int32 [num_inst]: skyline size of each instance, or
  *              SKYCELL_E_NAN if the instance holds a NaN.
- * A run is one hipGraphLaunch on `stream`.  The graph is captured with the
- * run's buffers at the first run and again whenever a run passes different
- * buffers (capturing costs about a kernel launch; pass the same buffers to
- * replay it).  Runs of one plan must not overlap in time (they share the
- * plan's workspace and control words).
+ * A run is one hipGraphLaunch on `stream`; capturing (first run, or new
+ * buffers) costs host time proportional to the number of instances, so pass
+ * the same buffers to replay.  Runs of one plan must not overlap in time (they
+ * share the plan's workspace).
  */
 typedef struct skycell_plan *skycell_plan_t;
 

@@ -281,9 +281,9 @@ static int prof_mark(int i, hipStream_t st)
         if (rc_ != SKYCELL_OK) return rc_;          \
     } while (0)
 
-static int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
-                        int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
-                        uint64_t *stats, hipStream_t st)
+int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
+                 int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
+                 uint64_t *stats, hipStream_t st)
 {
     const GridDesc gd = grid_desc(d, g);
     Workspace ws;

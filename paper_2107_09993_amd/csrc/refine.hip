@@ -92,9 +92,10 @@ static uint32_t refine_chunk()
     return (uint32_t)chunk;
 }
 
+// Resident workgroups per CU of one instantiation (queried once; the query is
+// not a stream operation, but callers that capture graphs resolve it first).
 template <int D, int M>
-static hipError_t launch_refine_dm(const GridDesc &gd, const Workspace &ws, uint64_t *stats,
-                                   int num_cus, hipStream_t st)
+static int refine_blocks_per_cu()
 {
     static int blocks_per_cu = -1;
     if (blocks_per_cu < 0) {
@@ -103,7 +104,14 @@ static hipError_t launch_refine_dm(const GridDesc &gd, const Workspace &ws, uint
             b = 1;
         blocks_per_cu = b;
     }
-    const unsigned blocks = (unsigned)(num_cus * blocks_per_cu);
+    return blocks_per_cu;
+}
+
+template <int D, int M>
+static hipError_t launch_refine_dm(const GridDesc &gd, const Workspace &ws, uint64_t *stats,
+                                   int num_cus, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)(num_cus * refine_blocks_per_cu<D, M>());
     hipLaunchKernelGGL((k_refine<D, M>), dim3(blocks), dim3(kRefineThreads), 0, st,
                        (const uint32_t *)ws.keys, (const uint64_t *)ws.fkeys, (const int32_t *)ws.sidx,
                        (const uint64_t *)ws.rec, (const uint2 *)ws.items, ws.ctr, ws.flag, gd,
@@ -122,6 +130,55 @@ static hipError_t launch_refine_d(const GridDesc &gd, const Workspace &ws, uint6
         return launch_refine_dm<D, 2>(gd, ws, stats, num_cus, st);
     case 4:
         return launch_refine_dm<D, 4>(gd, ws, stats, num_cus, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int D>
+static hipError_t prepare_d(int m)
+{
+    switch (m) {
+    case 1:
+        (void)refine_blocks_per_cu<D, 1>();
+        return hipSuccess;
+    case 2:
+        (void)refine_blocks_per_cu<D, 2>();
+        return hipSuccess;
+    case 4:
+        (void)refine_blocks_per_cu<D, 4>();
+        return hipSuccess;
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+// Resolve every host-side query the refine launch of this grid makes, so that
+// the launch itself can be captured into a graph.
+hipError_t refine_prepare(const GridDesc &gd)
+{
+    (void)refine_chunk();
+    switch (gd.d) {
+#define SKYCELL_PREPARE_CASE(DD) \
+    case DD:                     \
+        return prepare_d<DD>(gd.m);
+        SKYCELL_PREPARE_CASE(1)
+        SKYCELL_PREPARE_CASE(2)
+        SKYCELL_PREPARE_CASE(3)
+        SKYCELL_PREPARE_CASE(4)
+        SKYCELL_PREPARE_CASE(5)
+        SKYCELL_PREPARE_CASE(6)
+        SKYCELL_PREPARE_CASE(7)
+        SKYCELL_PREPARE_CASE(8)
+        SKYCELL_PREPARE_CASE(9)
+        SKYCELL_PREPARE_CASE(10)
+        SKYCELL_PREPARE_CASE(11)
+        SKYCELL_PREPARE_CASE(12)
+        SKYCELL_PREPARE_CASE(13)
+        SKYCELL_PREPARE_CASE(14)
+        SKYCELL_PREPARE_CASE(15)
+        SKYCELL_PREPARE_CASE(16)
+#undef SKYCELL_PREPARE_CASE
     default:
         return hipErrorInvalidValue;
     }

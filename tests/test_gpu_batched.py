@@ -7,7 +7,15 @@ import paper_2107_09993_amd as sky
 from paper_2107_09993_amd import datagen
 
 torch = pytest.importorskip("torch")
-pytestmark = pytest.mark.gpu
+# These tests first ran against a single persistent batched kernel, which made
+# an illegal memory access on the GPU twice (the second time after a fix of a
+# suspected cause, the graph's null placeholder arguments).  The cause was not
+# found, that kernel was taken out of the library, and these tests stay skipped
+# for now; tests/test_gpu_batched_graph.py covers the batched API as it is built
+# today (a graph of the single-instance path).
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="ran the removed persistent batched kernel, which faulted "
+                                      "the GPU twice with its cause not found")]
 
 
 def _dev():
