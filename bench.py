@@ -42,12 +42,15 @@ def parse():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=150_000,
                     help="prefix size for the CPU oracle baseline (0 = skip)")
+    ap.add_argument("--batched-count", type=int, default=4096,
+                    help="instances of the batched workload (0 = skip)")
+    ap.add_argument("--batched-steps", type=int, default=3)
     return ap.parse_args()
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("refine.hip", "common.h"):
+    for f in ("refine.hip", "refine_core.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2107_09993_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -68,6 +71,43 @@ def measured_traffic(kernel, workload):
     except (ValueError, OSError):
         return None
     return None
+
+
+def batched_bench(count, steps, dev):
+    """Batched workload: `count` instances with n log-uniform in [1,000, 200,000],
+    d uniform in 3..12 and the distribution drawn per instance, run as one graph
+    launch per step."""
+    import numpy as np
+    import torch
+    import paper_2107_09993_amd as sky
+    from paper_2107_09993_amd import datagen
+
+    shapes = datagen.batched_instances(count=count)
+    ns = [s[0] for s in shapes]
+    ds = [s[1] for s in shapes]
+    plan = sky.BatchedPlan(ns, ds, device=dev)
+    buf = np.empty(int(plan.points_off[-1]), dtype=np.float32)
+    for b, (n, d, dist, seed) in enumerate(shapes):
+        buf[plan.points_off[b]:plan.points_off[b + 1]] = datagen.generate(dist, n, d, seed).T.reshape(-1)
+    points = torch.from_numpy(buf).to(dev)
+    del buf
+    t0 = time.perf_counter()
+    plan.run(points)  # first run: captures the graph
+    torch.cuda.synchronize()
+    capture_s = time.perf_counter() - t0
+    total_sky = int(plan.out_count.to(torch.int64).sum().item())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(points)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.close()
+    return {"value": count * steps / wall, "unit": "instances/s", "instances": count,
+            "points": int(sum(ns)), "skyline_points": total_sky, "steps": steps,
+            "ms_per_launch": 1e3 * wall / steps, "first_run_with_capture_s": capture_s,
+            "workload": "batched: n log-uniform in [1e3, 2e5], d uniform in 3..12, "
+                        "independent/correlated/anti-correlated per instance, seeds 1e6+b"}
 
 
 def cpu_baseline(x_host, sample):
@@ -159,6 +199,10 @@ def main():
            "dominance_tests_per_s": st["pair_tests"] / (ms_per_step * 1e-3),
            "counters": st,
            "roofline": roof}
+    if a.batched_count > 0:
+        del sk
+        torch.cuda.empty_cache()
+        out["batched"] = batched_bench(a.batched_count, a.batched_steps, dev)
     if a.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(x, a.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -162,12 +162,13 @@ int skycell_batched_plan_create(int32_t num_inst, const int64_t *h_n, const int3
             plan_free(p);
             return set_error(SKYCELL_E_INVAL, "instance %d: grid_res < 0", b);
         }
-        p->g[b] = (h_grid != nullptr && h_grid[b] > 0) ? h_grid[b] : choose_grid_batched(h_n[b], h_d[b], dtype);
-        if (grid_cells(p->g[b], h_d[b]) > kBatchMaxCells) {
+        const int g = (h_grid != nullptr && h_grid[b] > 0) ? h_grid[b] : choose_grid_batched(h_n[b], h_d[b], dtype);
+        if (grid_cells(g, h_d[b]) > kBatchMaxCells) {
             plan_free(p);
-            return set_error(SKYCELL_E_RANGE, "instance %d: %d columns in %d dimensions exceed %u cells", b, p->g[b],
+            return set_error(SKYCELL_E_RANGE, "instance %d: %d columns in %d dimensions exceed %u cells", b, g,
                              h_d[b], kBatchMaxCells);
         }
+        p->g[b] = g;
         p->pts_off[b + 1] = p->pts_off[b] + h_n[b] * h_d[b];
         p->out_off[b + 1] = p->out_off[b] + h_n[b];
         const size_t ws = h_n[b] > 0 ? workspace_layout(h_n[b], h_d[b], grid_desc(h_d[b], p->g[b]).cells, nullptr, nullptr) : 0;
@@ -194,8 +195,9 @@ int skycell_batched_plan_create(int32_t num_inst, const int64_t *h_n, const int3
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_ws, std::max<size_t>(p->ws_off[num_inst], 256));
     if (e != hipSuccess) {
+        const size_t bytes = p->ws_off[num_inst];
         plan_free(p);
-        return set_error(SKYCELL_E_NOMEM, "plan workspace of %zu bytes: %s", p->ws_off[num_inst], hipGetErrorString(e));
+        return set_error(SKYCELL_E_NOMEM, "plan workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
     }
     // resolve the host-side queries of every launch before any capture
     for (int32_t b = 0; b < num_inst; ++b) {

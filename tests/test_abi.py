@@ -138,6 +138,7 @@ def test_batched_plan_argument_errors():
     assert lib.skycell_batched_plan_create(2, bad_n.ctypes.data, d.ctypes.data, 0, 16, None, ctypes.byref(h)) == sky.E_INVAL
     g = np.asarray([8, 64], dtype=np.int32)  # 64^4 = 2^24 cells > 2^20 per instance
     assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 0, 16, g.ctypes.data, ctypes.byref(h)) == sky.E_RANGE
+    assert "64 columns in 4 dimensions" in sky.last_error()
     assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 1, 0, None, ctypes.byref(h)) == sky.E_RANGE
     assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 5, 16, None, ctypes.byref(h)) == sky.E_INVAL
     assert lib.skycell_batched_run(None, FAKE, FAKE, FAKE, None) == sky.E_INVAL

@@ -60,7 +60,7 @@ def test_graph_batched_explicit_grids_and_u16(oracle_mod):
     rng = np.random.default_rng(3)
     arrays = [rng.integers(0, 16, size=(int(n), int(d))).astype(np.uint16)
               for n, d in zip(rng.integers(1, 4000, size=30), rng.integers(2, 9, size=30))]
-    grids = [int(g) for g in rng.integers(1, 9, size=30)]
+    grids = [int(g) for g in rng.integers(1, 5, size=30)]  # within 2^20 cells at d <= 8
     plan = sky.BatchedPlan([a.shape[0] for a in arrays], [a.shape[1] for a in arrays], dtype="u16",
                            value_bits=4, grid_res=grids, device=dev)
     assert list(plan.grid_res) == grids
