@@ -121,14 +121,18 @@ int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d,
 
 /*
  * Grid resolution the library uses when grid_res = 0: the autotuner's entry for
- * (d, n, dtype) if a tuning table is loaded, else a rule that keeps about one
- * to two cells per point under the cell budget (Section VI: rho <= log(n)/d).
+ * d and dtype whose log2 n is nearest to that of n (and at most 1 away) if a
+ * tuning table is loaded, else a rule that keeps about one to two cells per
+ * point under the cell budget (Section VI: rho <= log(n)/d).
  */
 int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res);
 
 /*
- * Load an autotuner table (text, one "d log2n dtype g" line per entry).  NULL
- * clears it.  Applies to all later calls in the process.
+ * Load an autotuner table (text, one "d log2n dtype g" line per entry; '#'
+ * starts a comment line).  dtype is SKYCELL_DTYPE_* for single calls and
+ * SKYCELL_DTYPE_* + 2 for the instances of a batched plan.  NULL clears the
+ * table.  Applies to all later calls in the process.  The Python binding loads
+ * the table shipped with the package unless SKYCELL_NO_TUNING is set.
  */
 int skycell_load_tuning(const char *path);
 
@@ -183,7 +187,8 @@ int skycell_profile_read(float *ms, int32_t count);
  *              skycell_compute_u16; ignored for F32).
  *   grid_res   host array [num_inst] of cells per dimension (0 entries, or a
  *              NULL array, let the autotuner choose per instance); each grid's
- *              index space is limited to 2^20 cells.
+ *              index space is limited to 32 cells per point (at least 2^16,
+ *              at most 2^24 cells).
  *   plan       receives an opaque handle owning the device workspace and the
  *              graph.  Creating a plan allocates device memory; it is not
  *              capture-safe.

@@ -70,6 +70,9 @@ def lib():
                  "skycell_plan_destroy"):
         getattr(L, name).restype = i32
     _lib = L
+    table = os.path.join(HERE, "tuning", "mi355x.txt")
+    if os.path.exists(table) and os.environ.get("SKYCELL_NO_TUNING") is None:
+        L.skycell_load_tuning(table.encode())
     return L
 
 

@@ -1,0 +1,105 @@
+"""Autotuner for the grid resolution (cells per dimension) of the skyline path.
+
+For every (d, n) on a grid of shapes it times the single-instance path on the
+three synthetic distributions for each candidate grid and keeps, per (d, n),
+the grid with the lowest mean time (the distribution of a future input is not
+known when the grid is chosen).  The result is a text table of
+"d log2n dtype g" lines that the library loads with skycell_load_tuning:
+
+    dtype 0 = binary32, single-instance calls (skycell_compute with grid_res 0)
+    dtype 2 = binary32, instances of a batched plan
+
+Run on the GPU the table is meant for:
+
+    python -m paper_2107_09993_amd.autotune --out paper_2107_09993_amd/tuning/mi355x.txt
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.txt")
+
+
+def candidate_grids(n, d, max_cells):
+    out = []
+    for g in (1, 2, 4, 8, 16, 32, 64):
+        r = (g - 1).bit_length()
+        if (1 << (r * d)) <= max_cells:
+            out.append(g)
+    return out
+
+
+def time_once(sky, torch, soa, n, d, g, reps):
+    s = sky.Skyline(n, d, grid_res=g, device=soa.device)
+    s.run(soa)
+    s.result()
+    best = math.inf
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(soa)
+        s.result()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def sweep(dims, sizes, reps=2, log=print):
+    import numpy as np
+    import torch
+    import paper_2107_09993_amd as sky
+    from paper_2107_09993_amd import datagen
+
+    dev = torch.device("cuda:0")
+    table = []
+    for d in dims:
+        for n in sizes:
+            # batched instances may use up to 32 cells per point (at most 2^24);
+            # single calls up to the library's 2^24-cell default budget
+            max_cells = min(1 << 24, max(1 << 16, 32 * n))
+            grids = candidate_grids(n, d, max_cells)
+            totals = dict.fromkeys(grids, 0.0)
+            for k, dist in enumerate(datagen.DISTRIBUTIONS):
+                x = datagen.generate(dist, n, d, seed=100 + k)
+                soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
+                for g in grids:
+                    totals[g] += time_once(sky, torch, soa, n, d, g, reps)
+                del soa
+            best = min(grids, key=lambda g: totals[g])
+            l2 = int(round(math.log2(n)))
+            table.append((d, l2, best))
+            log(json.dumps({"d": d, "n": n, "best": best,
+                            "mean_ms": {g: round(1e3 * t / 3, 3) for g, t in totals.items()}}))
+    return table
+
+
+def write_table(table, path):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        f.write("# d log2n dtype g  -- grid resolution with the lowest mean time over the\n")
+        f.write("# independent, correlated and anti-correlated inputs (paper_2107_09993_amd.autotune)\n")
+        for d, l2, g in table:
+            f.write("%d %d 0 %d\n" % (d, l2, g))
+            f.write("%d %d 2 %d\n" % (d, l2, g))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--dims", default="2,3,4,5,6,7,8,9,10,11,12")
+    ap.add_argument("--sizes", default="1000,4000,16000,64000,200000")
+    ap.add_argument("--reps", type=int, default=2)
+    a = ap.parse_args()
+    dims = [int(v) for v in a.dims.split(",")]
+    sizes = [int(v) for v in a.sizes.split(",")]
+    table = sweep(dims, sizes, a.reps, log=lambda s: print(s, flush=True))
+    write_table(table, a.out)
+    print("wrote", a.out, flush=True)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(HERE))
+    main()

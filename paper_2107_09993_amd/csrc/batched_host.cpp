@@ -22,7 +22,14 @@ using namespace skycell;
 namespace {
 
 constexpr int kBranches = 8;
-constexpr uint32_t kBatchMaxCells = 1u << 20;
+
+// Cell budget of one batched instance: 32 cells per point, at least 2^16 and at
+// most 2^24, so that the plan's workspace stays proportional to its points.
+uint64_t batch_max_cells(int64_t n)
+{
+    const uint64_t c = (uint64_t)n * 32u;
+    return c < (1u << 16) ? (1u << 16) : (c > (1u << 24) ? (1u << 24) : c);
+}
 
 }  // namespace
 
@@ -163,10 +170,10 @@ int skycell_batched_plan_create(int32_t num_inst, const int64_t *h_n, const int3
             return set_error(SKYCELL_E_INVAL, "instance %d: grid_res < 0", b);
         }
         const int g = (h_grid != nullptr && h_grid[b] > 0) ? h_grid[b] : choose_grid_batched(h_n[b], h_d[b], dtype);
-        if (grid_cells(g, h_d[b]) > kBatchMaxCells) {
+        if (grid_cells(g, h_d[b]) > batch_max_cells(h_n[b])) {
             plan_free(p);
-            return set_error(SKYCELL_E_RANGE, "instance %d: %d columns in %d dimensions exceed %u cells", b, g,
-                             h_d[b], kBatchMaxCells);
+            return set_error(SKYCELL_E_RANGE, "instance %d: %d columns in %d dimensions exceed %llu cells", b, g,
+                             h_d[b], (unsigned long long)batch_max_cells(h_n[b]));
         }
         p->g[b] = g;
         p->pts_off[b + 1] = p->pts_off[b] + h_n[b] * h_d[b];

@@ -2,6 +2,7 @@
 // choice, workspace layout and the launch sequence of the plain path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -82,7 +83,8 @@ static int default_grid(int64_t n, int d)
 }
 
 // Batched instances: the tuning table entry for (d, n) under dtype code
-// dtype + 2, else about two cells per point within 2^20 cells.
+// dtype + 2 (within the instance budget of 32 cells per point, at least 2^16
+// and at most 2^24), else about two cells per point within 2^20 cells.
 int choose_grid_batched(int64_t n, int d, int dtype)
 {
     {
@@ -97,7 +99,8 @@ int choose_grid_batched(int64_t n, int d, int dtype)
                 best = e.g;
             }
         }
-        if (best >= 1 && grid_cells(best, d) <= (1u << 20)) return best;
+        const uint64_t cap = std::min<uint64_t>(1u << 24, std::max<uint64_t>(1u << 16, (uint64_t)n * 32u));
+        if (best >= 1 && best_dist <= 2 && grid_cells(best, d) <= cap) return best;
     }
     double target = 2.0 * (double)n;
     if (target < 256.0) target = 256.0;
@@ -120,7 +123,8 @@ static int choose_grid(int64_t n, int d, int dtype)
             best = e.g;
         }
     }
-    if (best >= 1 && grid_cells(best, d) <= kMaxCells) return best;
+    // entries measured at sizes more than a factor ~2 away do not apply
+    if (best >= 1 && best_dist <= 1 && grid_cells(best, d) <= kMaxCells) return best;
     return default_grid(n, d);
 }
 

@@ -136,7 +136,7 @@ def test_batched_plan_argument_errors():
     assert lib.skycell_batched_plan_create(2, n.ctypes.data, bad_d.ctypes.data, 0, 16, None, ctypes.byref(h)) == sky.E_INVAL
     bad_n = np.asarray([10, -1], dtype=np.int64)
     assert lib.skycell_batched_plan_create(2, bad_n.ctypes.data, d.ctypes.data, 0, 16, None, ctypes.byref(h)) == sky.E_INVAL
-    g = np.asarray([8, 64], dtype=np.int32)  # 64^4 = 2^24 cells > 2^20 per instance
+    g = np.asarray([8, 64], dtype=np.int32)  # 64^4 = 2^24 cells > 2^16 for 20 points
     assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 0, 16, g.ctypes.data, ctypes.byref(h)) == sky.E_RANGE
     assert "64 columns in 4 dimensions" in sky.last_error()
     assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 1, 0, None, ctypes.byref(h)) == sky.E_RANGE
