@@ -49,6 +49,7 @@ enum {
     SKYCELL_E_HIP = -4,   /* a HIP runtime call or kernel launch failed                    */
     SKYCELL_E_NODEV = -5, /* no usable GPU                                                 */
     SKYCELL_E_NAN = -6    /* written to *out_count when the input holds a NaN              */
+    /* SKYCELL_E_RANGE is also written to *out_count when a pivot index is outside [0, n)   */
 };
 
 #define SKYCELL_MAX_D 16
@@ -58,7 +59,7 @@ enum {
 #define SKYCELL_DTYPE_U16 1
 
 /* Number of uint64 counters written by the *_stats variants (device memory). */
-#define SKYCELL_NUM_STATS 8
+#define SKYCELL_NUM_STATS 9
 /* Indices into the stats array.                                               */
 #define SKYCELL_STAT_NONEMPTY_CELLS 0  /* cells holding at least one point           */
 #define SKYCELL_STAT_SURVIVING_CELLS 1 /* non-empty cells not dominated (Def. 3)     */
@@ -68,6 +69,8 @@ enum {
 #define SKYCELL_STAT_PAIR_TESTS 5      /* candidate x query point domination tests   */
 #define SKYCELL_STAT_SKYLINE 6         /* number of skyline points                   */
 #define SKYCELL_STAT_GRID_RES 7        /* cells per dimension used                   */
+#define SKYCELL_STAT_PIVOT_REMOVED 8   /* points of surviving cells a pivot dominates
+                                          (pivoted calls; 0 otherwise)               */
 
 /*
  * Exact skyline of binary32 points (Definitions 1-2).
@@ -221,6 +224,116 @@ int skycell_batched_run(skycell_plan_t plan, const void *points, int32_t *out_id
 
 /* Waits for the device, then frees the plan's memory and graph. */
 int skycell_plan_destroy(skycell_plan_t plan);
+
+/*
+ * ------------------------------------------------------------------------
+ * Learned pivot proposer and pivot pre-filter.
+ *
+ * Not part of the paper's method: a small network scores points by how likely
+ * they are to be skyline points, and the best-scoring points serve as pivots.
+ * A pivot v removes every point q of a surviving cell that it dominates
+ * (Definition 1) before the counting sort, so q is neither refined nor used as
+ * a candidate.  The skyline is unchanged (dominance is transitive, so every
+ * remaining point keeps an undominated dominator in its lower cone): the
+ * result of every pivoted call equals skycell_compute's, whatever the pivots.
+ *
+ * Network: features f = (x[0..d), frac(x[k] * g) for k < d) of a point x, with
+ * the binary32 product x[k] * g and frac(t) = t - floor(t) (its position inside
+ * its column of Equation 1, g = the network's grid_res); then
+ *   h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), logit = w3 . h2 + b3,
+ * 2d -> 64 -> 64 -> 1.  Weights are kept in float32 (master copy, Adam state)
+ * and used as bfloat16 (round to nearest even); features and hidden
+ * activations are rounded to bfloat16 before each matrix product, which runs
+ * on the matrix cores with float32 accumulation.  Flat float32 parameter
+ * order: W1 [64][2d] (output-unit major), b1 [64], W2 [64][64], b2 [64],
+ * w3 [64], b3 — 128 d + 4289 values.
+ *
+ * Training minimises the mean binary cross-entropy of sigmoid(logit) against
+ * skyline labels (1 = skyline point) with Adam (beta1 0.9, beta2 0.999,
+ * epsilon 1e-8, bias-corrected).  Gradients pass straight through the
+ * bfloat16 roundings; the back-propagated pre-activation gradients are rounded
+ * to bfloat16 where they enter a matrix product.
+ *
+ * Points here are SoA blocks with a leading dimension: attribute k of point i
+ * at points[k * ld + i], ld >= n (ld = n for a whole array; a larger ld with an
+ * offset base pointer selects a mini-batch of a bigger array).
+ * Handles are bound to the device current at creation; every call on a handle
+ * must run with that device current.  Calls on one handle must not overlap.
+ * ------------------------------------------------------------------------
+ */
+#define SKYCELL_MLP_HIDDEN 64
+#define SKYCELL_MAX_PIVOTS 4096
+
+typedef struct skycell_mlp *skycell_mlp_t;
+
+/* Number of float32 parameters for d attributes (128 d + 4289). */
+int skycell_mlp_num_params(int32_t d, int64_t *count);
+
+/* New network for d attributes (1..16) and feature grid grid_res (>= 1):
+ * Glorot-uniform weights drawn from a counter-based generator (SplitMix64 of
+ * seed + parameter index), zero biases, zero Adam state.  Allocates device
+ * memory and synchronises the device. */
+int skycell_mlp_create(int32_t d, int32_t grid_res, uint64_t seed, skycell_mlp_t *mlp);
+int skycell_mlp_destroy(skycell_mlp_t mlp);
+
+/* Host float32 [count] parameters in the flat order above; count must equal
+ * skycell_mlp_num_params.  set also clears the Adam state and step count.
+ * Both synchronise the device. */
+int skycell_mlp_set_params(skycell_mlp_t mlp, const float *params, int64_t count);
+int skycell_mlp_get_params(skycell_mlp_t mlp, float *params, int64_t count);
+
+/* Host float32 [count]: the mean gradient of the last skycell_mlp_backward
+ * (get), or a gradient for the next skycell_mlp_adam_step (set).  Both
+ * synchronise the device. */
+int skycell_mlp_get_grads(skycell_mlp_t mlp, float *grads, int64_t count);
+int skycell_mlp_set_grads(skycell_mlp_t mlp, const float *grads, int64_t count);
+
+/* Logits of n points (device SoA with leading dimension ld) into device
+ * float32 logits [n]. */
+int skycell_mlp_score(skycell_mlp_t mlp, const float *points, int64_t ld, int64_t n, float *logits,
+                      void *stream);
+
+/* Mean loss and gradient over n points with device uint8 labels [n] (nonzero =
+ * skyline point); loss_out (device float32 [1]) may be NULL.  The gradient
+ * stays on the device for skycell_mlp_adam_step. */
+int skycell_mlp_backward(skycell_mlp_t mlp, const float *points, int64_t ld, const uint8_t *labels,
+                         int64_t n, float *loss_out, void *stream);
+
+/* One Adam step with learning rate lr on the current gradient. */
+int skycell_mlp_adam_step(skycell_mlp_t mlp, float lr, void *stream);
+
+/* skycell_mlp_backward followed by skycell_mlp_adam_step. */
+int skycell_mlp_train_step(skycell_mlp_t mlp, const float *points, int64_t ld, const uint8_t *labels,
+                           int64_t n, float lr, float *loss_out, void *stream);
+
+/* Binary file: "SKYMLP01", int32 d, grid_res, step, count, then float32
+ * parameters, first and second Adam moments (count each), little-endian. */
+int skycell_mlp_save(skycell_mlp_t mlp, const char *path);
+int skycell_mlp_load(const char *path, skycell_mlp_t *mlp);
+
+/* Training labels from a skyline result: labels[i] = 1 iff i is among
+ * idx[0 .. *count) (device pointers; a negative *count gives all zeros). */
+int skycell_skyline_labels(const int32_t *idx, const int32_t *count, int64_t n, uint8_t *labels,
+                           void *stream);
+
+/* Indices of the min(k, n) largest scores (device float32 [n]), largest first,
+ * equal scores (-0.0 == +0.0) by ascending index, into device int32 out_idx;
+ * 1 <= k <= SKYCELL_MAX_PIVOTS.  NaN scores take the place their bit pattern's
+ * order key gives them. */
+int skycell_topk(const float *scores, int64_t n, int32_t k, int32_t *out_idx, void *stream);
+
+/* skycell_compute (binary32) with the pre-filter by k caller-chosen pivots
+ * (device int32 pivot_idx [k], 0 <= k <= SKYCELL_MAX_PIVOTS).  A pivot index
+ * outside [0, n) makes *out_count = SKYCELL_E_RANGE.  stats as in
+ * skycell_compute_ws (may be NULL). */
+int skycell_compute_with_pivots(const float *points, int64_t n, int32_t d, int32_t grid_res,
+                                const int32_t *pivot_idx, int32_t k, int32_t *out_idx, int32_t *out_count,
+                                uint64_t *stats, void *stream);
+
+/* skycell_compute (binary32) with the k best-scoring points of mlp as pivots
+ * (mlp's d must equal d).  Output identical to skycell_compute. */
+int skycell_compute_pivoted(const float *points, int64_t n, int32_t d, int32_t grid_res, skycell_mlp_t mlp,
+                            int32_t k, int32_t *out_idx, int32_t *out_count, uint64_t *stats, void *stream);
 
 /* Text for the last nonzero return of the calling thread ("" if none). */
 const char *skycell_last_error(void);

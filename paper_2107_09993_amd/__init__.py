@@ -26,9 +26,11 @@ MAX_D = 16
 MAX_CELLS = 1 << 26
 DTYPE_F32 = 0
 DTYPE_U16 = 1
-NUM_STATS = 8
+NUM_STATS = 9
 STAT_NAMES = ("nonempty_cells", "surviving_cells", "survivor_points", "items", "cell_visits",
-              "pair_tests", "skyline", "grid_res")
+              "pair_tests", "skyline", "grid_res", "pivot_removed")
+MLP_HIDDEN = 64
+MAX_PIVOTS = 4096
 
 _lib = None
 
@@ -61,13 +63,35 @@ def lib():
     L.skycell_batched_offsets.argtypes = [p, p, p, p]
     L.skycell_batched_run.argtypes = [p, p, p, p, p]
     L.skycell_plan_destroy.argtypes = [p]
+    L.skycell_mlp_num_params.argtypes = [i32, ctypes.POINTER(i64)]
+    L.skycell_mlp_create.argtypes = [i32, i32, ctypes.c_uint64, ctypes.POINTER(p)]
+    L.skycell_mlp_destroy.argtypes = [p]
+    L.skycell_mlp_set_params.argtypes = [p, p, i64]
+    L.skycell_mlp_get_params.argtypes = [p, p, i64]
+    L.skycell_mlp_get_grads.argtypes = [p, p, i64]
+    L.skycell_mlp_set_grads.argtypes = [p, p, i64]
+    L.skycell_mlp_score.argtypes = [p, p, i64, i64, p, p]
+    L.skycell_mlp_backward.argtypes = [p, p, i64, p, i64, p, p]
+    L.skycell_mlp_adam_step.argtypes = [p, ctypes.c_float, p]
+    L.skycell_mlp_train_step.argtypes = [p, p, i64, p, i64, ctypes.c_float, p, p]
+    L.skycell_mlp_save.argtypes = [p, ctypes.c_char_p]
+    L.skycell_mlp_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(p)]
+    L.skycell_skyline_labels.argtypes = [p, p, i64, p, p]
+    L.skycell_topk.argtypes = [p, i64, i32, p, p]
+    L.skycell_compute_with_pivots.argtypes = [p, i64, i32, i32, p, i32, p, p, p, p]
+    L.skycell_compute_pivoted.argtypes = [p, i64, i32, i32, p, i32, p, p, p, p]
     L.skycell_last_error.argtypes = []
     L.skycell_last_error.restype = ctypes.c_char_p
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
                  "skycell_compute_ws", "skycell_choose_grid", "skycell_load_tuning",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
                  "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
-                 "skycell_plan_destroy"):
+                 "skycell_plan_destroy", "skycell_mlp_num_params", "skycell_mlp_create",
+                 "skycell_mlp_destroy", "skycell_mlp_set_params", "skycell_mlp_get_params",
+                 "skycell_mlp_get_grads", "skycell_mlp_set_grads", "skycell_mlp_score",
+                 "skycell_mlp_backward", "skycell_mlp_adam_step", "skycell_mlp_train_step",
+                 "skycell_mlp_save", "skycell_mlp_load", "skycell_skyline_labels", "skycell_topk",
+                 "skycell_compute_with_pivots", "skycell_compute_pivoted"):
         getattr(L, name).restype = i32
     _lib = L
     table = os.path.join(HERE, "tuning", "mi355x.txt")
@@ -283,3 +307,164 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned proposer
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device, stream=None):
+    import torch
+    return ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(device).cuda_stream)
+
+
+def mlp_num_params(d):
+    c = ctypes.c_int64(0)
+    _check(lib().skycell_mlp_num_params(int(d), ctypes.byref(c)))
+    return c.value
+
+
+class MLP:
+    """Pivot-scoring network 2d -> 64 -> 64 -> 1 on the current device (see
+    include/skycell.h for the features, the parameter order and the training
+    rule).  Points are [d, n] float32 tensors (SoA); a [d, N] tensor sliced as
+    x[:, a:b] is a mini-batch (its leading dimension is taken from the stride).
+    """
+
+    def __init__(self, d, grid_res, seed=0, _handle=None):
+        self.d, self.grid_res = int(d), int(grid_res)
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib().skycell_mlp_create(self.d, self.grid_res, ctypes.c_uint64(seed), ctypes.byref(h)))
+            _handle = h
+        self.handle = _handle
+        self.count = mlp_num_params(self.d)
+
+    @staticmethod
+    def load(path):
+        h = ctypes.c_void_p()
+        _check(lib().skycell_mlp_load(path.encode(), ctypes.byref(h)))
+        with open(path, "rb") as f:
+            f.read(8)
+            import struct
+            d, g = struct.unpack("<ii", f.read(8))
+        return MLP(d, g, _handle=h)
+
+    def save(self, path):
+        _check(lib().skycell_mlp_save(self.handle, path.encode()))
+
+    def _host(self, fn, values=None):
+        import numpy as np
+        buf = np.zeros(self.count, np.float32) if values is None else np.ascontiguousarray(values, np.float32)
+        if buf.shape != (self.count,):
+            raise ValueError("expected %d parameters" % self.count)
+        _check(fn(self.handle, buf.ctypes.data, self.count))
+        return buf
+
+    def get_params(self):
+        return self._host(lib().skycell_mlp_get_params)
+
+    def set_params(self, values):
+        self._host(lib().skycell_mlp_set_params, values)
+
+    def get_grads(self):
+        return self._host(lib().skycell_mlp_get_grads)
+
+    def set_grads(self, values):
+        self._host(lib().skycell_mlp_set_grads, values)
+
+    @staticmethod
+    def _soa(points):
+        if points.dim() != 2 or points.stride(1) != 1:
+            raise ValueError("points must be a [d, n] tensor with unit stride along n")
+        return points.shape[1], points.stride(0)
+
+    def score(self, points, out=None, stream=None):
+        import torch
+        n, ld = self._soa(points)
+        out = torch.empty(n, dtype=torch.float32, device=points.device) if out is None else out
+        _check(lib().skycell_mlp_score(self.handle, _ptr(points), ld, n, _ptr(out), _stream(points.device, stream)))
+        return out
+
+    def backward(self, points, labels, loss_out=None, stream=None):
+        n, ld = self._soa(points)
+        _check(lib().skycell_mlp_backward(self.handle, _ptr(points), ld, _ptr(labels), n, _ptr(loss_out),
+                                          _stream(points.device, stream)))
+
+    def adam_step(self, lr, device="cuda", stream=None):
+        import torch
+        _check(lib().skycell_mlp_adam_step(self.handle, ctypes.c_float(lr), _stream(torch.device(device), stream)))
+
+    def train_step(self, points, labels, lr, loss_out=None, stream=None):
+        n, ld = self._soa(points)
+        _check(lib().skycell_mlp_train_step(self.handle, _ptr(points), ld, _ptr(labels), n, ctypes.c_float(lr),
+                                            _ptr(loss_out), _stream(points.device, stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().skycell_mlp_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def skyline_labels(out_idx, out_count, n, stream=None):
+    """uint8 [n] device labels: 1 at the indices of a skyline result."""
+    import torch
+    labels = torch.empty(max(int(n), 1), dtype=torch.uint8, device=out_idx.device)
+    _check(lib().skycell_skyline_labels(_ptr(out_idx), _ptr(out_count), int(n), _ptr(labels),
+                                        _stream(out_idx.device, stream)))
+    return labels[:int(n)]
+
+
+def topk(scores, k, stream=None):
+    """Indices of the min(k, n) largest scores, largest first, ties by index."""
+    import torch
+    n = scores.numel()
+    kk = min(int(k), n)
+    out = torch.empty(max(kk, 1), dtype=torch.int32, device=scores.device)
+    _check(lib().skycell_topk(_ptr(scores.contiguous()), n, int(k), _ptr(out), _stream(scores.device, stream)))
+    return out[:kk]
+
+
+def _pivoted(points_soa, grid_res, pivots, mlp, k, return_stats, stream):
+    import torch
+    if points_soa.dtype != torch.float32 or not points_soa.is_contiguous() or points_soa.dim() != 2:
+        raise ValueError("points must be a contiguous float32 [d, n] tensor")
+    d, n = points_soa.shape
+    dev = points_soa.device
+    out_idx = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    out_count = torch.empty(1, dtype=torch.int32, device=dev)
+    stats = torch.zeros(NUM_STATS, dtype=torch.int64, device=dev) if return_stats else None
+    st = _stream(dev, stream)
+    if mlp is None:
+        piv = pivots.to(torch.int32).contiguous()
+        _check(lib().skycell_compute_with_pivots(_ptr(points_soa), n, d, int(grid_res), _ptr(piv), piv.numel(),
+                                                 _ptr(out_idx), _ptr(out_count), _ptr(stats), st))
+    else:
+        _check(lib().skycell_compute_pivoted(_ptr(points_soa), n, d, int(grid_res), mlp.handle, int(k),
+                                             _ptr(out_idx), _ptr(out_count), _ptr(stats), st))
+    c = int(out_count.item())
+    if c < 0:
+        raise SkycellError(c, "device reported %s" % ("NaN in input" if c == E_NAN else "a pivot index out of range"))
+    res = out_idx[:c].clone()
+    if return_stats:
+        return res, dict(zip(STAT_NAMES, (int(v) for v in stats.cpu().tolist())))
+    return res
+
+
+def compute_with_pivots(points_soa, pivots, grid_res=0, return_stats=False, stream=None):
+    """Exact skyline of [d, n] float32 points with the given pivot indices as
+    a pre-filter (the result equals compute's)."""
+    return _pivoted(points_soa, grid_res, pivots, None, 0, return_stats, stream)
+
+
+def compute_pivoted(points_soa, mlp, k=MAX_PIVOTS, grid_res=0, return_stats=False, stream=None):
+    """Exact skyline of [d, n] float32 points with the network's k best points
+    as pivots (the result equals compute's)."""
+    return _pivoted(points_soa, grid_res, None, mlp, k, return_stats, stream)

@@ -26,7 +26,7 @@ DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.txt")
 
 def candidate_grids(n, d, max_cells):
     out = []
-    for g in (1, 2, 4, 8, 16, 32, 64):
+    for g in (1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 48, 64):
         r = (g - 1).bit_length()
         if (1 << (r * d)) <= max_cells:
             out.append(g)

@@ -138,15 +138,21 @@ struct CellLoader {
 
 // Writes the first sorted position into the low half of the cell record and
 // the cell's work items: (first sorted position, (point count << 26) | cell).
+// With `recount`, the record's count field is rewritten from the scanned count.
 struct CellEmitter {
     uint32_t *rec_words;
     uint2 *items;
     uint32_t per_item;
+    bool recount;
     __device__ void operator()(uint64_t x, uint64_t prefix, uint64_t v) const
     {
         const uint32_t start = (uint32_t)prefix;
         rec_words[2 * x] = start;
         const uint32_t m = (uint32_t)v;
+        if (recount) {
+            const uint32_t hi = rec_words[2 * x + 1];
+            rec_words[2 * x + 1] = (hi & ~kRecCountSat) | (m < kRecCountSat ? m : kRecCountSat);
+        }
         const uint32_t it = (uint32_t)(v >> 32);
         const uint32_t ibase = (uint32_t)(prefix >> 32);
         for (uint32_t t = 0; t < it; ++t) {

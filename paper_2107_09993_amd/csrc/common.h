@@ -94,9 +94,12 @@ struct Workspace {
     uint32_t *ctr;        // small counters, see CtrIndex
 };
 
+// Rank of a point that the pivot pre-filter removed (never a real rank: n < 2^31).
+constexpr uint32_t kRankRemoved = 0xFFFFFFFFu;
+
 enum CtrIndex {
     kCtrItems = 0,     // number of refine work items
-    kCtrErr = 1,       // nonzero: NaN seen in the input
+    kCtrErr = 1,       // bit 0: NaN seen in the input; bit 1: pivot index out of range
     kCtrSurvPts = 2,   // number of surviving points
     kCtrHead = 8,      // kNumXcd refine work-queue heads, one per XCD share
     kCtrCount = 16     // number of 32-bit counters reserved
@@ -109,7 +112,10 @@ hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats,
 hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                                 int value_bits, const Workspace &ws, hipStream_t st);
 hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st);
-hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st);
+// recount: the cell counts were taken again after the pivot pre-filter; the
+// count field of every record is rewritten from them.
+hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st,
+                            bool recount = false);
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                           const Workspace &ws, int value_bits, hipStream_t st);
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,

@@ -146,11 +146,12 @@ __global__ void k_cell_scan_total(const uint64_t *block_sums, uint32_t nb, uint3
     }
 }
 
-hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st)
+hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st,
+                            bool recount)
 {
     const uint32_t m = (uint32_t)gd.m;
     CellLoader ld{ws.rec, ws.cnt, m};
-    CellEmitter em{(uint32_t *)ws.rec, ws.items, m};
+    CellEmitter em{(uint32_t *)ws.rec, ws.items, m, recount};
     hipError_t e = enqueue_scan<uint64_t>(ld, em, gd.cells, ws.block_sums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cell_scan_total, dim3(1), dim3(1), 0, st, (const uint64_t *)ws.block_sums,
@@ -181,7 +182,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts,
     const uint32_t x = cell_of[i];
     const uint64_t r = rec[x];
     if (!rec_surv(r)) return;
-    scatter_point(pts, n, d, value_bits, i, rec_start(r) + rank[i], keys, fkeys, sidx);
+    const uint32_t rk = rank[i];
+    if (rk == kRankRemoved) return;
+    scatter_point(pts, n, d, value_bits, i, rec_start(r) + rk, keys, fkeys, sidx);
 }
 
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,

@@ -207,10 +207,31 @@ struct CachedWs {
     size_t bytes = 0;
 };
 static std::mutex g_ws_mu;
-static std::map<std::pair<int, hipStream_t>, CachedWs> g_ws_cache;
+static std::map<std::pair<int, hipStream_t>, CachedWs> g_ws_cache[kCacheCount];
+
+int cached_buffer(int slot, int dev, hipStream_t st, size_t need, void **ptr)
+{
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    CachedWs &c = g_ws_cache[slot][std::make_pair(dev, st)];
+    if (c.bytes < need) {
+        if (c.ptr != nullptr) {
+            SKYCELL_HIP_CHECK(hipStreamSynchronize(st));
+            SKYCELL_HIP_CHECK(hipFree(c.ptr));
+            c.ptr = nullptr;
+            c.bytes = 0;
+        }
+        if (hipMalloc(&c.ptr, need) != hipSuccess) {
+            c.ptr = nullptr;
+            return fail(SKYCELL_E_NOMEM, "hipMalloc of %zu workspace bytes failed", need);
+        }
+        c.bytes = need;
+    }
+    *ptr = c.ptr;
+    return SKYCELL_OK;
+}
 
 // ---------------------------------------------------------------- validation
-static int validate(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
+int validate(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
                     int32_t value_bits, const int32_t *out_idx, const int32_t *out_count)
 {
     if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16)
@@ -228,7 +249,7 @@ static int validate(const void *points, int32_t dtype, int64_t n, int32_t d, int
     return SKYCELL_OK;
 }
 
-static int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out)
+int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out)
 {
     const int g = grid_res > 0 ? grid_res : choose_grid(n, d, dtype);
     if (grid_cells(g, d) > kMaxCells)
@@ -239,11 +260,6 @@ static int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, i
     return SKYCELL_OK;
 }
 
-#define SKYCELL_HIP_CHECK(expr)                                                          \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess) return fail(SKYCELL_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
 
 // ---------------------------------------------------------------- phase timing
 struct Profiler {
@@ -287,7 +303,7 @@ static int prof_mark(int i, hipStream_t st)
 
 int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
                  int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
-                 uint64_t *stats, hipStream_t st)
+                 uint64_t *stats, hipStream_t st, const PivotArgs *piv)
 {
     const GridDesc gd = grid_desc(d, g);
     Workspace ws;
@@ -300,8 +316,14 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
     SKYCELL_HIP_CHECK(launch_quantize_hist(points, dtype, n, gd, value_bits, ws, st));
     SKYCELL_PROF(1);
     SKYCELL_HIP_CHECK(launch_cell_prune(gd, ws, stats, st));
+    const bool pivots = piv != nullptr && piv->k > 0;
+    if (pivots) {
+        SKYCELL_HIP_CHECK(launch_pivot_gather((const float *)points, (uint32_t)n, d, piv->idx, piv->k, piv->ps,
+                                              ws.ctr, st));
+        SKYCELL_HIP_CHECK(launch_pivot_prune((const float *)points, (uint32_t)n, gd, ws, piv->ps, piv->k, stats, st));
+    }
     SKYCELL_PROF(2);
-    SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st));
+    SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st, pivots));
     SKYCELL_PROF(3);
     SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, value_bits, st));
     SKYCELL_PROF(4);
@@ -328,24 +350,7 @@ static int compute_owned(const void *points, int32_t dtype, int64_t n, int32_t d
     int dev = 0;
     SKYCELL_HIP_CHECK(hipGetDevice(&dev));
     void *ptr = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_ws_mu);
-        CachedWs &c = g_ws_cache[std::make_pair(dev, st)];
-        if (c.bytes < need) {
-            if (c.ptr != nullptr) {
-                SKYCELL_HIP_CHECK(hipStreamSynchronize(st));
-                SKYCELL_HIP_CHECK(hipFree(c.ptr));
-                c.ptr = nullptr;
-                c.bytes = 0;
-            }
-            if (hipMalloc(&c.ptr, need) != hipSuccess) {
-                c.ptr = nullptr;
-                return fail(SKYCELL_E_NOMEM, "hipMalloc of %zu workspace bytes failed", need);
-            }
-            c.bytes = need;
-        }
-        ptr = c.ptr;
-    }
+    if ((rc = cached_buffer(kCacheWorkspace, dev, st, need, &ptr)) != SKYCELL_OK) return rc;
     return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, ptr, nullptr, st);
 }
 

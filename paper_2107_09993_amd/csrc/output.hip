@@ -25,7 +25,8 @@ __global__ void k_output_total(const uint64_t *block_sums, uint32_t nb, const ui
                                int32_t *out_count, uint64_t *stats)
 {
     const uint64_t tot = block_sums[nb];
-    *out_count = ctr[kCtrErr] ? (int32_t)SKYCELL_E_NAN : (int32_t)tot;
+    const uint32_t err = ctr[kCtrErr];
+    *out_count = (err & 1u) ? (int32_t)SKYCELL_E_NAN : (err & 2u) ? (int32_t)SKYCELL_E_RANGE : (int32_t)tot;
     if (stats != nullptr) stats[SKYCELL_STAT_SKYLINE] = tot;
 }
 

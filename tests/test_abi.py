@@ -21,7 +21,9 @@ def _declared():
 def test_header_declares_expected_entry_points():
     names = _declared()
     for want in ("skycell_compute", "skycell_compute_u16", "skycell_compute_ws",
-                 "skycell_workspace_bytes", "skycell_choose_grid", "skycell_last_error"):
+                 "skycell_workspace_bytes", "skycell_choose_grid", "skycell_last_error",
+                 "skycell_mlp_create", "skycell_mlp_train_step", "skycell_mlp_score",
+                 "skycell_topk", "skycell_compute_pivoted", "skycell_compute_with_pivots"):
         assert want in names
 
 
@@ -34,7 +36,8 @@ def test_library_exports_every_declared_symbol():
 def test_constants_match_header():
     src = open(HEADER).read()
     assert "SKYCELL_MAX_D 16" in src and sky.MAX_D == 16
-    assert "SKYCELL_NUM_STATS 8" in src and sky.NUM_STATS == 8
+    assert "SKYCELL_NUM_STATS 9" in src and sky.NUM_STATS == 9 == len(sky.STAT_NAMES)
+    assert "SKYCELL_MAX_PIVOTS 4096" in src and sky.MAX_PIVOTS == 4096
     for name, val in (("SKYCELL_E_INVAL", -1), ("SKYCELL_E_RANGE", -2), ("SKYCELL_E_NOMEM", -3),
                       ("SKYCELL_E_HIP", -4), ("SKYCELL_E_NODEV", -5), ("SKYCELL_E_NAN", -6)):
         assert re.search(r"%s\s*=\s*%d" % (name, val), src)
@@ -143,3 +146,59 @@ def test_batched_plan_argument_errors():
     assert lib.skycell_batched_plan_create(2, n.ctypes.data, d.ctypes.data, 5, 16, None, ctypes.byref(h)) == sky.E_INVAL
     assert lib.skycell_batched_run(None, FAKE, FAKE, FAKE, None) == sky.E_INVAL
     assert lib.skycell_plan_destroy(None) == sky.E_INVAL
+
+
+# ---------------------------------------------------------------- learned path
+def test_mlp_num_params():
+    from oracle import learned
+    for d in (1, 3, 10, 16):
+        assert sky.mlp_num_params(d) == learned.num_params(d) == 128 * d + 4289
+    assert sky.mlp_num_params(10) == 5569
+    with pytest.raises(sky.SkycellError):
+        sky.mlp_num_params(0)
+
+
+def test_mlp_create_argument_errors():
+    lib = sky.lib()
+    h = ctypes.c_void_p()
+    assert lib.skycell_mlp_create(0, 4, 1, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_mlp_create(17, 4, 1, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_mlp_create(4, 0, 1, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_mlp_create(4, 4, 1, None) == sky.E_INVAL
+    assert lib.skycell_mlp_destroy(None) == sky.OK
+
+
+def test_mlp_load_rejects_bad_files(tmp_path):
+    lib = sky.lib()
+    h = ctypes.c_void_p()
+    assert lib.skycell_mlp_load(str(tmp_path / "missing.bin").encode(), ctypes.byref(h)) == sky.E_INVAL
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTANMLP" + bytes(64))
+    assert lib.skycell_mlp_load(str(bad).encode(), ctypes.byref(h)) == sky.E_INVAL
+    import struct
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"SKYMLP01" + struct.pack("<iiii", 4, 8, 0, 128 * 4 + 4289) + bytes(16))
+    assert lib.skycell_mlp_load(str(short).encode(), ctypes.byref(h)) == sky.E_INVAL
+    assert "truncated" in sky.last_error()
+    wrong = tmp_path / "wrong.bin"
+    wrong.write_bytes(b"SKYMLP01" + struct.pack("<iiii", 4, 8, 0, 99))
+    assert lib.skycell_mlp_load(str(wrong).encode(), ctypes.byref(h)) == sky.E_INVAL
+
+
+def test_pivoted_argument_errors():
+    lib = sky.lib()
+    # k outside [0, 4096], null pivots, null network: all rejected before any HIP call
+    assert lib.skycell_compute_with_pivots(FAKE, 10, 4, 8, FAKE, 4097, FAKE, FAKE, None, None) == sky.E_INVAL
+    assert lib.skycell_compute_with_pivots(FAKE, 10, 4, 8, FAKE, -1, FAKE, FAKE, None, None) == sky.E_INVAL
+    assert lib.skycell_compute_with_pivots(FAKE, 10, 4, 8, None, 5, FAKE, FAKE, None, None) == sky.E_INVAL
+    assert lib.skycell_compute_with_pivots(FAKE, 10, 0, 8, FAKE, 5, FAKE, FAKE, None, None) == sky.E_INVAL
+    assert lib.skycell_compute_with_pivots(FAKE, 10, 8, 10, FAKE, 5, FAKE, FAKE, None, None) == sky.E_RANGE
+    assert lib.skycell_compute_pivoted(FAKE, 10, 4, 8, None, 16, FAKE, FAKE, None, None) == sky.E_INVAL
+    assert lib.skycell_topk(FAKE, 10, 0, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_topk(FAKE, 10, 4097, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_topk(FAKE, -1, 5, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_topk(None, 10, 5, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_skyline_labels(FAKE, FAKE, -1, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_skyline_labels(None, FAKE, 5, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_mlp_score(None, FAKE, 10, 10, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_mlp_train_step(None, FAKE, 10, FAKE, 10, ctypes.c_float(0.1), None, None) == sky.E_INVAL

@@ -1,0 +1,303 @@
+"""GPU parity of the learned pivot proposer against the CPU oracle.
+
+Forward logits, loss, gradients and Adam steps of the hand-written MFMA kernels
+are compared with oracle/learned.py (float64 with the same bfloat16 rounding
+points).  Tolerances follow from the arithmetic: the kernels accumulate in
+float32 (relative error about K * 2^-24 per sum of K terms) and a bfloat16
+rounding decision (8 significant bits) can only differ from the oracle's when a
+value lies that close to a rounding boundary; each such flip moves one
+activation by one bfloat16 unit in the last place (at most 2^-7 of its value).
+The bound used for a logit is that every hidden activation flipped at once.
+
+Top-k and the pivot pre-filter are integer work and must match exactly; the
+pivoted skyline must equal the oracle's skyline bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import learned as L
+import paper_2107_09993_amd as sky
+from paper_2107_09993_amd import datagen
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def soa(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, np.float32).T)).to(DEV)
+
+
+def rand_params(d, seed, scale=0.25):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0.0, scale, L.num_params(d))
+    return p.astype(np.float32)
+
+
+def logit_bound(params, x, g):
+    """Largest logit change if every hidden activation moved by 2^-7 of itself."""
+    fw = L.forward(params.astype(np.float64), x, g)
+    w3 = np.abs(fw["w3"])
+    s2 = np.abs(fw["h2"]) @ w3
+    sens1 = np.abs(fw["W2"]).T @ w3          # |dz/dh1| upper bound per unit
+    s1 = np.abs(fw["h1"]) @ sens1
+    return 2.0 ** -7 * (s1 + s2), fw["z"]
+
+
+# ---------------------------------------------------------------- forward
+@pytest.mark.parametrize("d,n,g", [(1, 37, 4), (3, 1000, 8), (8, 4099, 4), (10, 20011, 4), (16, 3001, 2)])
+def test_forward_matches_oracle(d, n, g):
+    x = datagen.generate("anticorrelated", n, d, 100 + d)
+    p = rand_params(d, d)
+    m = sky.MLP(d, g)
+    m.set_params(p)
+    z = m.score(soa(x)).cpu().numpy().astype(np.float64)
+    bound, zo = logit_bound(p, x, g)
+    err = np.abs(z - zo)
+    assert np.all(err <= bound + 1e-5 * (1 + np.abs(zo))), float(np.max(err - bound))
+    assert np.quantile(err / (1 + np.abs(zo)), 0.9) <= 1e-4
+    m.close()
+
+
+def test_forward_on_a_minibatch_slice():
+    d, n = 6, 5000
+    x = datagen.generate("independent", n, d, 5)
+    p = rand_params(d, 9)
+    m = sky.MLP(d, 8)
+    m.set_params(p)
+    full = soa(x)
+    part = m.score(full[:, 1234:3456]).cpu().numpy()
+    whole = m.score(full).cpu().numpy()
+    assert np.array_equal(part, whole[1234:3456])
+    m.close()
+
+
+# ---------------------------------------------------------------- backward
+def grad_blocks(d):
+    b1 = 64 * 2 * d
+    return {"W1": slice(0, b1), "b1": slice(b1, b1 + 64), "W2": slice(b1 + 64, b1 + 64 + 4096),
+            "b2": slice(b1 + 4160, b1 + 4224), "w3": slice(b1 + 4224, b1 + 4288),
+            "b3": slice(b1 + 4288, b1 + 4289)}
+
+
+@pytest.mark.parametrize("d,n,g", [(2, 777, 4), (10, 8192 + 13, 4), (16, 3000, 2)])
+def test_backward_matches_oracle(d, n, g):
+    x = datagen.generate("anticorrelated", n, d, 7 + d)
+    y = (np.random.default_rng(d).random(n) < 0.6).astype(np.uint8)
+    p = rand_params(d, 3 * d)
+    m = sky.MLP(d, g)
+    m.set_params(p)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    m.backward(soa(x), torch.from_numpy(y).to(DEV), loss_out=loss)
+    g_gpu = m.get_grads().astype(np.float64)
+    lo, g_or = L.loss_and_grad(p.astype(np.float64), x, y, g)
+    assert abs(float(loss.item()) - lo) <= 1e-4 * max(1.0, abs(lo))
+    for name, sl in grad_blocks(d).items():
+        a, b = g_gpu[sl], g_or[sl]
+        scale = max(np.max(np.abs(b)), 1e-12)
+        assert np.linalg.norm(a - b) <= 5e-3 * max(np.linalg.norm(b), 1e-12), name
+        assert np.max(np.abs(a - b)) <= 1e-2 * scale, name
+    m.close()
+
+
+def test_backward_all_padding_tail_and_single_point():
+    d, g = 4, 4
+    x = datagen.generate("correlated", 1, d, 1)
+    y = np.array([1], np.uint8)
+    p = rand_params(d, 1)
+    m = sky.MLP(d, g)
+    m.set_params(p)
+    m.backward(soa(x), torch.from_numpy(y).to(DEV))
+    lo, g_or = L.loss_and_grad(p.astype(np.float64), x, y, g)
+    g_gpu = m.get_grads().astype(np.float64)
+    assert np.linalg.norm(g_gpu - g_or) <= 5e-3 * np.linalg.norm(g_or)
+    m.close()
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_matches_oracle():
+    d = 5
+    p = rand_params(d, 4)
+    rng = np.random.default_rng(8)
+    m = sky.MLP(d, 4)
+    m.set_params(p)
+    pm, m1, m2 = p.astype(np.float64), np.zeros(L.num_params(d)), np.zeros(L.num_params(d))
+    for t in range(1, 4):
+        gr = (rng.normal(0, 1e-2, L.num_params(d)) * (rng.random(L.num_params(d)) < 0.9)).astype(np.float32)
+        m.set_grads(gr)
+        m.adam_step(0.01)
+        pm, m1, m2 = L.adam_step(pm, gr.astype(np.float64), m1, m2, t, 0.01)
+        got = m.get_params().astype(np.float64)
+        np.testing.assert_allclose(got, pm, rtol=2e-6, atol=2e-7)
+    m.close()
+
+
+def test_save_load_roundtrip(tmp_path):
+    d, g = 7, 8
+    m = sky.MLP(d, g, seed=123)
+    x = soa(datagen.generate("independent", 3000, d, 2))
+    y = torch.ones(3000, dtype=torch.uint8, device=DEV)
+    m.train_step(x, y, 1e-3)
+    path = str(tmp_path / "net.bin")
+    m.save(path)
+    m2 = sky.MLP.load(path)
+    assert (m2.d, m2.grid_res) == (d, g)
+    assert np.array_equal(m.get_params(), m2.get_params())
+    assert torch.equal(m.score(x), m2.score(x))
+    # the Adam state came along: one more step moves both alike (the gradient
+    # sums use float atomics, so only up to their rounding)
+    m.train_step(x, y, 1e-3)
+    m2.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(m.get_params(), m2.get_params(), rtol=1e-5, atol=1e-6)
+    m.close()
+    m2.close()
+
+
+def test_create_is_seeded_and_glorot_bounded():
+    d = 10
+    a = sky.MLP(d, 4, seed=5).get_params()
+    b = sky.MLP(d, 4, seed=5).get_params()
+    c = sky.MLP(d, 4, seed=6).get_params()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    blk = grad_blocks(d)
+    lim1 = np.sqrt(6.0 / (2 * d + 64))
+    assert np.all(np.abs(a[blk["W1"]]) <= lim1) and np.abs(a[blk["W1"]]).max() > 0.9 * lim1
+    assert np.all(a[blk["b1"]] == 0) and np.all(a[blk["b2"]] == 0) and a[blk["b3"]][0] == 0
+
+
+def test_training_lowers_the_loss():
+    d, n = 6, 100_000
+    x = datagen.generate("anticorrelated", n, d, 31)
+    xs = soa(x)
+    idx = sky.compute(xs, layout="dn")
+    cnt = torch.tensor([idx.numel()], dtype=torch.int32, device=DEV)
+    y = sky.skyline_labels(idx, cnt, n)
+    assert int(y.sum().item()) == idx.numel()
+    m = sky.MLP(d, sky.choose_grid(n, d), seed=1)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    m.backward(xs, y, loss_out=loss)
+    first = float(loss.item())
+    for epoch in range(30):
+        for a in range(0, n, 16384):
+            m.train_step(xs[:, a:a + 16384], y[a:a + 16384], 3e-3)
+    m.backward(xs, y, loss_out=loss)
+    last = float(loss.item())
+    assert last < 0.9 * first, (first, last)
+    m.close()
+
+
+# ---------------------------------------------------------------- labels
+def test_skyline_labels():
+    n = 1000
+    idx = torch.tensor([3, 7, 999, 0], dtype=torch.int32, device=DEV)
+    cnt = torch.tensor([3], dtype=torch.int32, device=DEV)
+    y = sky.skyline_labels(idx, cnt, n).cpu().numpy()
+    want = np.zeros(n, np.uint8); want[[3, 7, 999]] = 1
+    assert np.array_equal(y, want)
+    neg = torch.tensor([-6], dtype=torch.int32, device=DEV)
+    assert int(sky.skyline_labels(idx, neg, n).sum().item()) == 0
+
+
+# ---------------------------------------------------------------- top-k
+TOPK_CASES = [
+    ("single", 1, 1), ("k_above_n", 10, 4096), ("ties_small", 5000, 100),
+    ("random_mid", 100_003, 4096), ("few_values_big", 2_000_000, 4096),
+    ("all_equal", 50_000, 4096), ("signed_zeros", 30_000, 777), ("k_is_n", 4096, 4096),
+]
+
+
+@pytest.mark.parametrize("name,n,k", TOPK_CASES, ids=[c[0] for c in TOPK_CASES])
+def test_topk_matches_oracle(name, n, k):
+    rng = np.random.default_rng(n + k)
+    if name in ("ties_small", "few_values_big"):
+        s = rng.integers(-20, 20, n).astype(np.float32) / 4
+    elif name == "all_equal":
+        s = np.full(n, 0.5, np.float32)
+    elif name == "signed_zeros":
+        s = np.where(rng.random(n) < 0.5, np.float32(-0.0), np.float32(0.0))
+        s[rng.random(n) < 0.01] = 1.0
+    else:
+        s = rng.normal(0, 3, n).astype(np.float32)
+    got = sky.topk(torch.from_numpy(s).to(DEV), k).cpu().numpy()
+    assert np.array_equal(got, L.topk(s, k))
+
+
+# ---------------------------------------------------------------- pivot pre-filter
+def surviving_mask(x, g):
+    """Definition 3 per point (oracle): the point's cell is not dominated."""
+    c = oracle.cell_coords(x, g)
+    cells, inv = np.unique(c, axis=0, return_inverse=True)
+    dom = oracle.cells_dominated(cells.astype(np.int32))
+    return ~dom[inv.reshape(-1)]
+
+
+PIVOT_CASES = [
+    ("anti_d4", "anticorrelated", 20000, 4, 8, "l1", 4096),
+    ("ind_d8", "independent", 30000, 8, 4, "random", 1000),
+    ("corr_d3", "correlated", 25000, 3, 16, "l1", 64),
+    ("anti_d10", "anticorrelated", 40000, 10, 2, "l1", 4096),
+    ("ties_d5", "small_integers", 20000, 5, 4, "random", 300),
+    ("k_above_n", "independent", 500, 3, 4, "l1", 4096),
+]
+
+
+@pytest.mark.parametrize("name,dist,n,d,g,how,k", PIVOT_CASES, ids=[c[0] for c in PIVOT_CASES])
+def test_compute_with_pivots(oracle_mod, name, dist, n, d, g, how, k):
+    if dist == "small_integers":
+        x = datagen.small_integers(n, d, seed=3, high=6)
+    else:
+        x = datagen.generate(dist, n, d, 40 + d)
+    rng = np.random.default_rng(n)
+    if how == "l1":   # pivots: smallest coordinate sums first (oracle-side choice)
+        piv = L.topk(-x.astype(np.float64).sum(axis=1).astype(np.float32), k)
+    else:
+        piv = rng.choice(n, min(k, n), replace=False).astype(np.int32)
+    got, st = sky.compute_with_pivots(soa(x), torch.from_numpy(piv).to(DEV), grid_res=g, return_stats=True)
+    want = oracle.skyline_sfs(x)
+    assert np.array_equal(got.cpu().numpy(), want)
+    kk = min(k, n)
+    removed = surviving_mask(x, g) & L.dominated_by_any(x, x[piv[:kk]])
+    assert st["pivot_removed"] == int(removed.sum())
+    assert st["survivor_points"] == int(surviving_mask(x, g).sum()) - int(removed.sum())
+
+
+def test_pivot_index_out_of_range_is_reported():
+    x = soa(datagen.generate("independent", 1000, 3, 1))
+    with pytest.raises(sky.SkycellError):
+        sky.compute_with_pivots(x, torch.tensor([5, 1000], dtype=torch.int32, device=DEV), grid_res=4)
+    with pytest.raises(sky.SkycellError):
+        sky.compute_with_pivots(x, torch.tensor([-1], dtype=torch.int32, device=DEV), grid_res=4)
+    # and the library keeps working afterwards
+    idx = sky.compute_with_pivots(x, torch.tensor([5], dtype=torch.int32, device=DEV), grid_res=4)
+    assert np.array_equal(idx.cpu().numpy(), sky.compute(x, layout="dn", grid_res=4).cpu().numpy())
+
+
+@pytest.mark.parametrize("k", [1, 100, 4096])
+def test_compute_pivoted_equals_oracle(oracle_mod, k):
+    d, n = 8, 60000
+    x = datagen.generate("anticorrelated", n, d, 77)
+    m = sky.MLP(d, 4, seed=k)
+    got, st = sky.compute_pivoted(soa(x), m, k=k, return_stats=True)
+    assert np.array_equal(got.cpu().numpy(), oracle.skyline_sfs(x))
+    assert st["skyline"] == got.numel()
+    m.close()
+
+
+def test_pivoted_headline_size_sampled(oracle_mod):
+    """n = 2e7, d = 10 anti-correlated (the learned workload): pivoted equals
+    plain exactly; sampled indices are checked against the oracle."""
+    d, n = 10, 20_000_000
+    x = datagen.generate("anticorrelated", n, d, 0)
+    xs = soa(x)
+    m = sky.MLP(d, 4, seed=0)
+    piv = sky.compute_pivoted(xs, m, k=4096)
+    plain = sky.compute(xs, layout="dn")
+    assert torch.equal(piv, plain)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(n, 48, replace=False)).astype(np.int32)
+    res = oracle.is_skyline(x, sample)
+    got = np.isin(sample, piv.cpu().numpy())
+    assert np.array_equal(got, res)
+    m.close()
