@@ -376,9 +376,11 @@ class MLP:
 
     @staticmethod
     def _soa(points):
-        if points.dim() != 2 or points.stride(1) != 1:
+        if points.dim() != 2 or (points.shape[1] > 1 and points.stride(1) != 1):
             raise ValueError("points must be a [d, n] tensor with unit stride along n")
-        return points.shape[1], points.stride(0)
+        n = points.shape[1]
+        # a single row's stride is arbitrary; any ld >= n addresses it
+        return n, points.stride(0) if points.shape[0] > 1 else max(n, 1)
 
     def score(self, points, out=None, stream=None):
         import torch
