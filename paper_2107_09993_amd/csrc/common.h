@@ -121,12 +121,6 @@ hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc 
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st);
 hipError_t refine_prepare(const GridDesc &gd);
-// Wave-uniform refine over chunks of at most 64 sorted points per aligned
-// Morton block of 2^bb cells (launch_block_chunks builds the chunk list).
-hipError_t launch_block_chunks(const GridDesc &gd, const Workspace &ws, int bb, uint64_t *stats, hipStream_t st);
-hipError_t launch_refine_wave(const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus, int dtype,
-                              int value_bits, hipStream_t st);
-hipError_t refine_wave_prepare(const GridDesc &gd);
 hipError_t launch_output(int64_t n, const Workspace &ws, int32_t *out_idx, int32_t *out_count,
                          uint64_t *stats, hipStream_t st);
 hipError_t launch_write_zero_count(int32_t *out_count, hipStream_t st);

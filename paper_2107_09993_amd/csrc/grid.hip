@@ -159,58 +159,6 @@ hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *s
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ chunks
-// Refine work items of the wave-uniform refine: the sorted points of every
-// aligned Morton block of 2^bb cells, cut into chunks of at most 64.
-struct BlockChunks {
-    const uint64_t *rec;
-    uint2 *items;
-    uint32_t bb;
-    uint32_t nblocks;
-    uint32_t cells;
-    __device__ void range(uint64_t b, uint32_t &s, uint32_t &e) const
-    {
-        s = rec_start(rec[(uint32_t)b << bb]);
-        e = b + 1 < nblocks ? rec_start(rec[(uint32_t)(b + 1) << bb]) : rec_start(rec[cells]);
-    }
-    __device__ uint32_t operator()(uint64_t b) const
-    {
-        uint32_t s, e;
-        range(b, s, e);
-        return (e - s + (uint32_t)kWave - 1u) / (uint32_t)kWave;
-    }
-    __device__ void operator()(uint64_t b, uint32_t prefix, uint32_t v) const
-    {
-        if (v == 0u) return;
-        uint32_t s, e;
-        range(b, s, e);
-        for (uint32_t t = 0; t < v; ++t) {
-            const uint32_t first = s + t * (uint32_t)kWave;
-            const uint32_t left = e - first;
-            items[prefix + t] = make_uint2(first, left < (uint32_t)kWave ? left : (uint32_t)kWave);
-        }
-    }
-};
-
-__global__ void k_block_scan_total(const uint64_t *block_sums, uint32_t nb, uint32_t *ctr, uint64_t *stats)
-{
-    const uint64_t tot = block_sums[nb];
-    ctr[kCtrItems] = (uint32_t)tot;
-    for (int h = 0; h < kNumXcd; ++h) ctr[kCtrHead + h] = 0u;
-    if (stats != nullptr) stats[SKYCELL_STAT_ITEMS] = tot;
-}
-
-hipError_t launch_block_chunks(const GridDesc &gd, const Workspace &ws, int bb, uint64_t *stats, hipStream_t st)
-{
-    const uint32_t nblocks = gd.cells >> bb;
-    BlockChunks bc{ws.rec, ws.items, (uint32_t)bb, nblocks, gd.cells};
-    hipError_t e = enqueue_scan<uint32_t>(bc, bc, nblocks, ws.block_sums, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_block_scan_total, dim3(1), dim3(1), 0, st, (const uint64_t *)ws.block_sums,
-                       scan_tiles(nblocks), ws.ctr, stats);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ K4
 // Counting-sort scatter of the points of surviving cells: slot = first sorted
 // position of the cell + the point's rank from the histogram atomic, so the

@@ -141,33 +141,6 @@ static int items_per_lane(int d)
     return env > 0 ? env : items_per_group(d);
 }
 
-// Refine form: the wave-uniform cone walk over chunks of 64 points (default),
-// or the lane-per-item walk (SKYCELL_REFINE=lane, kept for comparison).
-static bool refine_lanes()
-{
-    static int env = -1;
-    if (env < 0) {
-        const char *v = getenv("SKYCELL_REFINE");
-        env = (v != nullptr && strcmp(v, "lane") == 0) ? 1 : 0;
-    }
-    return env == 1;
-}
-
-// Morton block bits of the refine chunks: chunks never cross an aligned block
-// of 2^bb cells, so a chunk's corner stays within one column of its points in
-// bb dimensions.  SKYCELL_BLOCK_BITS overrides the default min(d, r*d).
-static int block_bits(const GridDesc &gd)
-{
-    static int env = -2;
-    if (env == -2) {
-        const char *v = getenv("SKYCELL_BLOCK_BITS");
-        env = v ? atoi(v) : -1;
-    }
-    const int total = gd.r * gd.d;
-    int bb = env >= 0 ? env : gd.d;
-    return bb < total ? bb : total;
-}
-
 GridDesc grid_desc(int d, int g)
 {
     GridDesc gd;
@@ -351,15 +324,10 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
     }
     SKYCELL_PROF(2);
     SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st, pivots));
-    const bool lanes = refine_lanes();
-    if (!lanes) SKYCELL_HIP_CHECK(launch_block_chunks(gd, ws, block_bits(gd), stats, st));
     SKYCELL_PROF(3);
     SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, value_bits, st));
     SKYCELL_PROF(4);
-    if (lanes)
-        SKYCELL_HIP_CHECK(launch_refine(n, gd, ws, stats, cus, st));
-    else
-        SKYCELL_HIP_CHECK(launch_refine_wave(gd, ws, stats, cus, dtype, value_bits, st));
+    SKYCELL_HIP_CHECK(launch_refine(n, gd, ws, stats, cus, st));
     SKYCELL_PROF(5);
     SKYCELL_HIP_CHECK(launch_output(n, ws, out_idx, out_count, stats, st));
     SKYCELL_PROF(6);

@@ -158,8 +158,6 @@ static hipError_t prepare_d(int m)
 hipError_t refine_prepare(const GridDesc &gd)
 {
     (void)refine_chunk();
-    const hipError_t e = refine_wave_prepare(gd);
-    if (e != hipSuccess) return e;
     switch (gd.d) {
 #define SKYCELL_PREPARE_CASE(DD) \
     case DD:                     \
