@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--batched-count", type=int, default=4096,
                     help="instances of the batched workload (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run three device-to-device copies of 1 GiB (the reference "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -141,6 +144,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if a.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     x = datagen.generate(a.dist, a.n, a.d, a.seed)
     soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
     g = a.grid if a.grid else sky.choose_grid(a.n, a.d)

@@ -102,6 +102,10 @@ static int refine_blocks_per_cu()
         int b = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_refine<D, M>, kRefineThreads, 0) != hipSuccess || b < 1)
             b = 1;
+        // SKYCELL_REFINE_BLOCKS caps the resident workgroups per CU (tuning sweeps)
+        const char *v = getenv("SKYCELL_REFINE_BLOCKS");
+        const int cap = v ? atoi(v) : 0;
+        if (cap >= 1 && cap < b) b = cap;
         blocks_per_cu = b;
     }
     return blocks_per_cu;

@@ -43,6 +43,11 @@ constexpr uint64_t kHigh = 0x8080808080808080ull;
 constexpr uint64_t kOnes = 0x0101010101010101ull;
 constexpr int kRefillMin = 8;  // idle lanes that trigger handing out new items
 
+// Hides a value from the optimiser (an empty register constraint, no
+// instruction), so that OR-accumulated arithmetic stays arithmetic instead of
+// being turned back into per-element compares and lane-mask chains.
+__device__ __forceinline__ void opaque(uint32_t &v) { asm("" : "+v"(v)); }
+
 // Exact keys of sorted point i: D words, with 16- or 8-byte vector loads when
 // D allows (rows are 4*D bytes apart from a 256-byte aligned base).
 template <int D>
@@ -233,20 +238,26 @@ __device__ void refine_loop(const RefineView &v, Feeder &feed, uint32_t &visits,
             ++visits;
         }
 
-        // ---- deferred exact test (Definition 1)
+        // ---- deferred exact test (Definition 1), branch-free over the query
+        // points: e dominates q iff no coordinate of e exceeds q's (max(e,q) ^ q
+        // is zero in every dimension) and some coordinate differs
         if (exok) {
+            uint32_t dom = 0u;
 #pragma unroll
             for (int t = 0; t < M; ++t) {
-                if ((exmask & alive) & (1u << t)) {
-                    bool le = true, ne = false;
+                uint32_t gt = 0u, ne = 0u;
 #pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        le = le && (e[k] <= q[t][k]);
-                        ne = ne || (e[k] != q[t][k]);
-                    }
-                    if (le && ne) alive &= ~(1u << t);
+                for (int k = 0; k < D; ++k) {
+                    const uint32_t qv = q[t][k];
+                    uint32_t g = max(e[k], qv) ^ qv, x = e[k] ^ qv;
+                    opaque(g);
+                    opaque(x);
+                    gt |= g;
+                    ne |= x;
                 }
+                dom |= (gt == 0u && ne != 0u) ? (1u << t) : 0u;
             }
+            alive &= ~(dom & exmask);
             exmask = 0u;
         }
 
@@ -262,24 +273,25 @@ __device__ void refine_loop(const RefineView &v, Feeder &feed, uint32_t &visits,
             for (int cnd = 0; cnd < 2; ++cnd) {
                 if (cnd == 1 && !c1ok) break;
                 const uint32_t cidx = cur + (uint32_t)cnd;
-                uint32_t pass = 0u;
+                // query points screened: alive, and not the candidate itself
+                const uint32_t self = cidx - qstart;
+                const uint32_t act = alive & ~(self < (uint32_t)M ? (1u << self) : 0u);
+                uint32_t le_bits = 0u, lt_bits = 0u;
 #pragma unroll
                 for (int t = 0; t < M; ++t) {
-                    if ((alive & (1u << t)) && cidx != qstart + (uint32_t)t) {
-                        bool le = true, lt = true;
+                    uint64_t nle = 0ull, nlt = 0ull;
 #pragma unroll
-                        for (int w = 0; w < FW; ++w) {
-                            const uint64_t diff = qf[t][w] - (cnd == 0 ? f0[w] : f1[w]);
-                            le = le && ((diff & kHigh) == kHigh);
-                            lt = lt && (((diff - kOnes) & kHigh) == kHigh);
-                        }
-                        if (lt)
-                            alive &= ~(1u << t);
-                        else if (le)
-                            pass |= 1u << t;
-                        ++tests;
+                    for (int w = 0; w < FW; ++w) {
+                        const uint64_t diff = qf[t][w] - (cnd == 0 ? f0[w] : f1[w]);
+                        nle |= ~diff & kHigh;
+                        nlt |= ~(diff - kOnes) & kHigh;
                     }
+                    le_bits |= nle == 0ull ? (1u << t) : 0u;
+                    lt_bits |= nlt == 0ull ? (1u << t) : 0u;
                 }
+                tests += (uint32_t)__popc(act);
+                alive &= ~(lt_bits & act);
+                uint32_t pass = le_bits & ~lt_bits & act;
                 pass &= alive;
                 if (pass == 0u) {
                     ++adv;
