@@ -40,11 +40,13 @@ def parse():
     ap.add_argument("--dist", default="anticorrelated")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=150_000,
+    ap.add_argument("--cpu-sample", type=int, default=250_000,
                     help="prefix size for the CPU oracle baseline (0 = skip)")
     ap.add_argument("--batched-count", type=int, default=4096,
                     help="instances of the batched workload (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--learned-n", type=int, default=20_000_000,
+                    help="points of the learned-proposer evaluation (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run three device-to-device copies of 1 GiB (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -111,6 +113,22 @@ def batched_bench(count, steps, dev):
             "ms_per_launch": 1e3 * wall / steps, "first_run_with_capture_s": capture_s,
             "workload": "batched: n log-uniform in [1e3, 2e5], d uniform in 3..12, "
                         "independent/correlated/anti-correlated per instance, seeds 1e6+b"}
+
+
+def learned_bench(n, dev):
+    """Pivoted vs plain skyline on the learned workload (n anti-correlated
+    points in d = 10) with the committed network, k = 4096 pivots; random and
+    smallest-coordinate-sum pivots for comparison."""
+    import paper_2107_09993_amd as sky
+    from paper_2107_09993_amd import learned
+    if not os.path.exists(learned.DEFAULT_NET):
+        return {"skipped": "no trained network at %s" % learned.DEFAULT_NET}
+    mlp = sky.MLP.load(learned.DEFAULT_NET)
+    res = learned.evaluate(mlp, n=n, d=mlp.d, k=sky.MAX_PIVOTS, reps=3, device=dev)
+    mlp.close()
+    res["workload"] = "anticorrelated n=%d d=%d seed=0, top-4096 pivots of the network" % (n, mlp.d)
+    res["speedup_vs_plain"] = res["learned"]["speedup_vs_plain"]
+    return res
 
 
 def cpu_baseline(x_host, sample):
@@ -213,6 +231,9 @@ def main():
         del sk
         torch.cuda.empty_cache()
         out["batched"] = batched_bench(a.batched_count, a.batched_steps, dev)
+    if a.learned_n > 0:
+        torch.cuda.empty_cache()
+        out["learned"] = learned_bench(a.learned_n, dev)
     if a.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(x, a.cpu_sample)
     print(json.dumps(out), flush=True)
