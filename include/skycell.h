@@ -131,13 +131,25 @@ int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d,
 int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res);
 
 /*
- * Load an autotuner table (text, one "d log2n dtype g" line per entry; '#'
- * starts a comment line).  dtype is SKYCELL_DTYPE_* for single calls and
+ * Load an autotuner table (text, one "d log2n dtype g [form]" line per entry,
+ * form 0 = lane, 1 = wave refine, see skycell_set_refine_form; '#' starts a
+ * comment line).  dtype is SKYCELL_DTYPE_* for single calls and
  * SKYCELL_DTYPE_* + 2 for the instances of a batched plan.  NULL clears the
  * table.  Applies to all later calls in the process.  The Python binding loads
  * the table shipped with the package unless SKYCELL_NO_TUNING is set.
  */
 int skycell_load_tuning(const char *path);
+
+/*
+ * Refine form for all later calls in the process: -1 = chosen per call (the
+ * tuning table's form for the call's d, n and grid, else the wave form when
+ * the grid has at most n/32 cells), 0 = lane form (one lane walks the lower
+ * cone of a few points of one cell), 1 = wave form (one wave walks the cone of
+ * up to 63 points of one cell and tests every candidate against all of them).
+ * The result never depends on the form; this is for tests and tuning sweeps.
+ * SKYCELL_REFINE_FORM=lane|wave in the environment sets it at the first call.
+ */
+int skycell_set_refine_form(int32_t form);
 
 /*
  * Byte offsets of the workspace's sub-buffers for (n, d, grid_res) (grid_res 0 =
@@ -233,7 +245,10 @@ int skycell_plan_destroy(skycell_plan_t plan);
  * they are to be skyline points, and the best-scoring points serve as pivots.
  * A pivot v removes every point q of a surviving cell that it dominates
  * (Definition 1) before the counting sort, so q is neither refined nor used as
- * a candidate.  The skyline is unchanged (dominance is transitive, so every
+ * a candidate.  The pass is gated: points i = j * (n / m), j < m = min(n,
+ * 16384) (integer division) are screened first, and the pass runs only when
+ * at least 1 in 100 of the sampled points of surviving cells is dominated by
+ * a pivot (or none was sampled); otherwise no point is removed.  The skyline is unchanged (dominance is transitive, so every
  * remaining point keeps an undominated dominator in its lower cone): the
  * result of every pivoted call equals skycell_compute's, whatever the pivots.
  *

@@ -208,7 +208,7 @@ int skycell_batched_plan_create(int32_t num_inst, const int64_t *h_n, const int3
     }
     // resolve the host-side queries of every launch before any capture
     for (int32_t b = 0; b < num_inst; ++b) {
-        if ((e = refine_prepare(grid_desc(h_d[b], p->g[b]))) != hipSuccess) {
+        if ((e = refine_prepare(pipeline_desc(h_n[b], h_d[b], p->g[b], dtype))) != hipSuccess) {
             plan_free(p);
             return set_error(SKYCELL_E_HIP, "preparing instance %d: %s", b, hipGetErrorString(e));
         }

@@ -37,6 +37,11 @@ __host__ __device__ constexpr int fine_words(int d) { return (d + 7) / 8; }
 // Default number of query points per refine work item, by dimensionality.
 __host__ __device__ constexpr int items_per_group(int d) { return d <= 8 ? 4 : 2; }
 
+// Query points per work item of the wave form of the refine (one wave per item
+// of one cell; the item's count field has 6 bits).  GridDesc::m takes this
+// value when a call uses the wave form.
+constexpr int kWaveItemPoints = 63;
+
 // Number of XCDs (each with its own L2) that workgroups are spread over
 // round-robin; the refine gives each one a contiguous share of the work.
 constexpr int kNumXcd = 8;
@@ -101,6 +106,8 @@ enum CtrIndex {
     kCtrItems = 0,     // number of refine work items
     kCtrErr = 1,       // bit 0: NaN seen in the input; bit 1: pivot index out of range
     kCtrSurvPts = 2,   // number of surviving points
+    kCtrPivSampled = 3,  // pivot pre-filter: sampled points of surviving cells
+    kCtrPivHit = 4,      // ... of which a pivot dominates
     kCtrHead = 8,      // kNumXcd refine work-queue heads, one per XCD share
     kCtrCount = 16     // number of 32-bit counters reserved
 };
@@ -121,6 +128,9 @@ hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc 
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st);
 hipError_t refine_prepare(const GridDesc &gd);
+// Wave form (refine_wave.hip), used when gd.m == kWaveItemPoints.
+hipError_t launch_refine_wave(const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus, hipStream_t st);
+hipError_t refine_wave_prepare(const GridDesc &gd);
 hipError_t launch_output(int64_t n, const Workspace &ws, int32_t *out_idx, int32_t *out_count,
                          uint64_t *stats, hipStream_t st);
 hipError_t launch_write_zero_count(int32_t *out_count, hipStream_t st);

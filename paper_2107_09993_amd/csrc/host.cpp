@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -49,6 +50,7 @@ struct TuneEntry {
     int log2n;
     int dtype;
     int g;
+    int form;  // refine form for this grid: 0 lane, 1 wave, -1 not given
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
@@ -139,6 +141,47 @@ static int items_per_lane(int d)
         env = (e == 1 || e == 2 || e == 4) ? e : 0;
     }
     return env > 0 ? env : items_per_group(d);
+}
+
+// Refine form of a call: SKYCELL_REFINE_FORM=lane|wave (sweeps), else the
+// tuning table's form for this (d, n, dtype) and grid, else the wave form when
+// the grid is very coarse (at least 32 points per cell of the index space on
+// average), where cells hold enough points to keep a wave busy.
+static std::atomic<int> g_form_override{-2};  // -2 unread, -1 none, 0 lane, 1 wave
+
+static int refine_form(int64_t n, int d, int g, int dtype)
+{
+    int ov = g_form_override.load();
+    if (ov == -2) {
+        const char *v = getenv("SKYCELL_REFINE_FORM");
+        const int e = v == nullptr ? -1 : (strcmp(v, "wave") == 0 ? 1 : (strcmp(v, "lane") == 0 ? 0 : -1));
+        int expected = -2;
+        g_form_override.compare_exchange_strong(expected, e);
+        ov = g_form_override.load();
+    }
+    if (ov >= 0) return ov;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        int best = -1, best_dist = 1 << 30;
+        const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
+        for (const TuneEntry &e : g_tune) {
+            if (e.d != d || e.g != g || e.form < 0 || (e.dtype != dtype && e.dtype != dtype + 2)) continue;
+            const int dist = std::abs(e.log2n - l2);
+            if (dist < best_dist) {
+                best_dist = dist;
+                best = e.form;
+            }
+        }
+        if (best >= 0 && best_dist <= 2) return best;
+    }
+    return (uint64_t)n >= 32ull * grid_cells(g, d) ? 1 : 0;
+}
+
+GridDesc pipeline_desc(int64_t n, int d, int g, int dtype)
+{
+    GridDesc gd = grid_desc(d, g);
+    if (refine_form(n, d, g, dtype) == 1) gd.m = kWaveItemPoints;
+    return gd;
 }
 
 GridDesc grid_desc(int d, int g)
@@ -305,7 +348,7 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
                  int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
                  uint64_t *stats, hipStream_t st, const PivotArgs *piv)
 {
-    const GridDesc gd = grid_desc(d, g);
+    const GridDesc gd = pipeline_desc(n, d, g, dtype);
     Workspace ws;
     workspace_layout(n, d, gd.cells, &ws, (char *)workspace);
     int dev = 0;
@@ -421,6 +464,13 @@ int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res)
     return ok();
 }
 
+int skycell_set_refine_form(int32_t form)
+{
+    if (form < -1 || form > 1) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0 or 1", form);
+    g_form_override.store(form);
+    return ok();
+}
+
 int skycell_load_tuning(const char *path)
 {
     std::vector<TuneEntry> entries;
@@ -431,9 +481,12 @@ int skycell_load_tuning(const char *path)
         while (fgets(line, sizeof(line), f)) {
             if (line[0] == '#') continue;
             TuneEntry e;
-            if (sscanf(line, "%d %d %d %d", &e.d, &e.log2n, &e.dtype, &e.g) == 4 && e.d >= 1 &&
-                e.d <= SKYCELL_MAX_D && e.g >= 1)
+            e.form = -1;
+            const int got = sscanf(line, "%d %d %d %d %d", &e.d, &e.log2n, &e.dtype, &e.g, &e.form);
+            if (got >= 4 && e.d >= 1 && e.d <= SKYCELL_MAX_D && e.g >= 1) {
+                if (got < 5 || (e.form != 0 && e.form != 1)) e.form = -1;
                 entries.push_back(e);
+            }
         }
         fclose(f);
     }

@@ -26,6 +26,8 @@ int set_error(int code, const char *fmt, ...);  // records the thread's error te
 int clear_error();                               // clears it, returns SKYCELL_OK
 uint64_t grid_cells(int g, int d);               // 2^(r*d), saturated above the cell budget
 GridDesc grid_desc(int d, int g);
+// grid_desc with the refine form chosen for an instance of n points
+GridDesc pipeline_desc(int64_t n, int d, int g, int dtype);
 int choose_grid_batched(int64_t n, int d, int dtype);
 int device_cus(int dev);
 // Enqueue the whole single-instance path (n > 0) on `st` with a workspace of

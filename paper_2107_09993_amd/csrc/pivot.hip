@@ -7,6 +7,10 @@
 //           index cut (three passes, smallest first), one selection pass and a
 //           one-workgroup bitonic sort of the k selected (key, index) pairs;
 //   gather  the pivots' exact keys and packed screening columns;
+//   gate    a sample of 2^14 points is screened first; the full pass runs only
+//           when pivots remove at least 1% of the sampled points of
+//           surviving cells (otherwise the pass only counts the points again;
+//           the plain path is the fallback and the result is the same);
 //   prune   every point of a surviving cell (Definition 3) is tested against
 //           the pivots; a pivot v that dominates it (Definition 1) removes it
 //           from the refine, as a query and as a candidate.  The skyline is
@@ -239,52 +243,50 @@ hipError_t launch_pivot_gather(const float *pts, uint32_t n, int d, const int32_
 // ------------------------------------------------------------------ prune
 constexpr int kPruneThreads = 256;
 constexpr int kPivotChunk = 1024;
+constexpr uint32_t kPivotSample = 16384;  // points screened by the gate of the pre-filter
 
 __global__ void k_zero_u32(uint32_t *__restrict__ p, uint32_t count)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// Screening words (query side, top bits set, padding 0x7F) and exact keys of
+// point i.
 template <int D>
-__global__ __launch_bounds__(kPruneThreads) void k_pivot_prune(const float *__restrict__ pts, uint32_t n,
-                                                               const uint32_t *__restrict__ cell_of,
-                                                               const uint64_t *__restrict__ rec,
-                                                               const uint32_t *__restrict__ pkeys,
-                                                               const uint64_t *__restrict__ pfine, uint32_t k,
-                                                               uint32_t *__restrict__ rank,
-                                                               uint32_t *__restrict__ cnt,
-                                                               uint64_t *__restrict__ stats)
+__device__ __forceinline__ void query_words(const float *__restrict__ pts, uint32_t n, uint32_t i,
+                                            uint32_t (&qk)[D], uint64_t (&qh)[fine_words(D)])
+{
+    constexpr int FW = fine_words(D);
+    constexpr uint64_t H = 0x8080808080808080ull;
+    bool nan = false;
+#pragma unroll
+    for (int w = 0; w < FW; ++w) qh[w] = 0ull;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const float v = pts[(size_t)t * n + i];
+        qk[t] = f32_key(v);
+        qh[t >> 3] |= (uint64_t)column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan) << (8 * (t & 7));
+    }
+#pragma unroll
+    for (int t = D; t < 8 * FW; ++t) qh[t >> 3] |= 0x7Full << (8 * (t & 7));
+#pragma unroll
+    for (int w = 0; w < FW; ++w) qh[w] |= H;
+}
+
+// Whether some pivot dominates the calling thread's point (Definition 1),
+// scanning the pivots in chunks staged through LDS by the whole workgroup.
+// Every thread of the workgroup must call it (alive = false for threads
+// without a point); the workgroup leaves early once no thread is alive.
+template <int D>
+__device__ __forceinline__ bool dominated_by_pivot(bool alive, const uint32_t (&qk)[D],
+                                                   const uint64_t (&qh)[fine_words(D)],
+                                                   const uint32_t *__restrict__ pkeys,
+                                                   const uint64_t *__restrict__ pfine, uint32_t k,
+                                                   uint64_t *s_f)
 {
     constexpr int FW = fine_words(D);
     constexpr uint64_t H = 0x8080808080808080ull, L1 = 0x0101010101010101ull;
-    __shared__ uint64_t s_f[kPivotChunk * FW];
-
-    const uint32_t i = blockIdx.x * kPruneThreads + threadIdx.x;
-    uint32_t x = 0u;
-    bool cand = false;
-    if (i < n) {
-        x = cell_of[i];
-        cand = rec_surv(rec[x]);
-    }
-    uint32_t qk[D];
-    uint64_t qh[FW];
-    if (cand) {
-        bool nan = false;
-#pragma unroll
-        for (int w = 0; w < FW; ++w) qh[w] = 0ull;
-#pragma unroll
-        for (int t = 0; t < D; ++t) {
-            const float v = pts[(size_t)t * n + i];
-            qk[t] = f32_key(v);
-            qh[t >> 3] |= (uint64_t)column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan) << (8 * (t & 7));
-        }
-#pragma unroll
-        for (int t = D; t < 8 * FW; ++t) qh[t >> 3] |= 0x7Full << (8 * (t & 7));
-#pragma unroll
-        for (int w = 0; w < FW; ++w) qh[w] |= H;
-    }
-
-    bool alive = cand, removed = false;
+    bool removed = false;
     for (uint32_t base = 0; base < k; base += kPivotChunk) {
         if (__syncthreads_or(alive) == 0) break;
         const uint32_t cnt_c = k - base < (uint32_t)kPivotChunk ? k - base : (uint32_t)kPivotChunk;
@@ -321,6 +323,62 @@ __global__ __launch_bounds__(kPruneThreads) void k_pivot_prune(const float *__re
         }
         __syncthreads();
     }
+    return removed;
+}
+
+// Gate of the pre-filter: a sample of the points (every stride-th) of
+// surviving cells is screened against the pivots; the full pass below runs
+// only when pivots remove at least 1 in 100 of them.
+template <int D>
+__global__ __launch_bounds__(kPruneThreads) void k_pivot_sample(const float *__restrict__ pts, uint32_t n,
+                                                                uint32_t stride, uint32_t nsample,
+                                                                const uint32_t *__restrict__ cell_of,
+                                                                const uint64_t *__restrict__ rec,
+                                                                const uint32_t *__restrict__ pkeys,
+                                                                const uint64_t *__restrict__ pfine, uint32_t k,
+                                                                uint32_t *__restrict__ ctr)
+{
+    __shared__ uint64_t s_f[kPivotChunk * fine_words(D)];
+    const uint32_t j = blockIdx.x * kPruneThreads + threadIdx.x;
+    const uint32_t i = j * stride;
+    bool cand = false;
+    if (j < nsample && i < n) cand = rec_surv(rec[cell_of[i]]);
+    uint32_t qk[D];
+    uint64_t qh[fine_words(D)];
+    if (cand) query_words<D>(pts, n, i, qk, qh);
+    const bool removed = dominated_by_pivot<D>(cand, qk, qh, pkeys, pfine, k, s_f);
+    const uint64_t bc = __ballot(cand), br = __ballot(removed);
+    if (__lane_id() == 0) {
+        if (bc) atomicAdd(&ctr[kCtrPivSampled], (uint32_t)__popcll(bc));
+        if (br) atomicAdd(&ctr[kCtrPivHit], (uint32_t)__popcll(br));
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kPruneThreads) void k_pivot_prune(const float *__restrict__ pts, uint32_t n,
+                                                               const uint32_t *__restrict__ cell_of,
+                                                               const uint64_t *__restrict__ rec,
+                                                               const uint32_t *__restrict__ pkeys,
+                                                               const uint64_t *__restrict__ pfine, uint32_t k,
+                                                               uint32_t *__restrict__ rank,
+                                                               uint32_t *__restrict__ cnt,
+                                                               const uint32_t *__restrict__ ctr,
+                                                               uint64_t *__restrict__ stats)
+{
+    __shared__ uint64_t s_f[kPivotChunk * fine_words(D)];
+    const uint32_t i = blockIdx.x * kPruneThreads + threadIdx.x;
+    // the sample decides for the whole grid (the same value in every thread)
+    const bool use = (uint64_t)ctr[kCtrPivHit] * 100u >= (uint64_t)ctr[kCtrPivSampled];
+    uint32_t x = 0u;
+    bool cand = false;
+    if (i < n) {
+        x = cell_of[i];
+        cand = rec_surv(rec[x]);
+    }
+    uint32_t qk[D];
+    uint64_t qh[fine_words(D)];
+    if (cand && use) query_words<D>(pts, n, i, qk, qh);
+    const bool removed = use ? dominated_by_pivot<D>(cand, qk, qh, pkeys, pfine, k, s_f) : false;
     if (cand) rank[i] = removed ? kRankRemoved : atomicAdd(&cnt[x], 1u);
     if (stats != nullptr) {
         const uint64_t b = __ballot(removed);
@@ -335,13 +393,19 @@ hipError_t launch_pivot_prune(const float *pts, uint32_t n, const GridDesc &gd, 
     unsigned zb = (gd.cells + 255u) / 256u;
     if (zb > 4096) zb = 4096;
     hipLaunchKernelGGL(k_zero_u32, dim3(zb ? zb : 1), dim3(256), 0, st, ws.cnt, gd.cells);
+    const uint32_t nsample = n < kPivotSample ? n : kPivotSample;
+    const uint32_t stride = n / nsample;
+    const dim3 sgrid((nsample + kPruneThreads - 1) / kPruneThreads);
     const dim3 grid((n + kPruneThreads - 1) / kPruneThreads);
     switch (gd.d) {
-#define SKYCELL_PRUNE_CASE(DD)                                                                               \
-    case DD:                                                                                                 \
-        hipLaunchKernelGGL(k_pivot_prune<DD>, grid, dim3(kPruneThreads), 0, st, pts, n,                      \
-                           (const uint32_t *)ws.cell_of, (const uint64_t *)ws.rec, (const uint32_t *)ps.pkeys, \
-                           (const uint64_t *)ps.pfine, k, ws.rank, ws.cnt, stats);                           \
+#define SKYCELL_PRUNE_CASE(DD)                                                                                  \
+    case DD:                                                                                                    \
+        hipLaunchKernelGGL(k_pivot_sample<DD>, sgrid, dim3(kPruneThreads), 0, st, pts, n, stride, nsample,      \
+                           (const uint32_t *)ws.cell_of, (const uint64_t *)ws.rec, (const uint32_t *)ps.pkeys,  \
+                           (const uint64_t *)ps.pfine, k, ws.ctr);                                             \
+        hipLaunchKernelGGL(k_pivot_prune<DD>, grid, dim3(kPruneThreads), 0, st, pts, n,                         \
+                           (const uint32_t *)ws.cell_of, (const uint64_t *)ws.rec, (const uint32_t *)ps.pkeys,  \
+                           (const uint64_t *)ps.pfine, k, ws.rank, ws.cnt, (const uint32_t *)ws.ctr, stats);   \
         break;
         SKYCELL_PRUNE_CASE(1)
         SKYCELL_PRUNE_CASE(2)

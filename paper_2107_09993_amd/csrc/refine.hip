@@ -162,6 +162,7 @@ static hipError_t prepare_d(int m)
 hipError_t refine_prepare(const GridDesc &gd)
 {
     (void)refine_chunk();
+    if (gd.m == kWaveItemPoints) return refine_wave_prepare(gd);
     switch (gd.d) {
 #define SKYCELL_PREPARE_CASE(DD) \
     case DD:                     \
@@ -192,6 +193,7 @@ hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uin
                          int num_cus, hipStream_t st)
 {
     (void)n;
+    if (gd.m == kWaveItemPoints) return launch_refine_wave(gd, ws, stats, num_cus, st);
     switch (gd.d) {
 #define SKYCELL_REFINE_CASE(DD) \
     case DD:                    \

@@ -7,8 +7,10 @@ Adam, one mini-batch after another.  Evaluation: the pivoted skyline against
 the plain one on a larger anti-correlated input, with the network's top-k
 points, random points and the smallest-coordinate-sum points as pivots.
 
-    python -m paper_2107_09993_amd.learned train --out paper_2107_09993_amd/nets/anti_d10.bin
-    python -m paper_2107_09993_amd.learned eval --net paper_2107_09993_amd/nets/anti_d10.bin
+    python -m paper_2107_09993_amd.learned train --dist anticorrelated   # -> nets/anti_d10.bin
+    python -m paper_2107_09993_amd.learned eval --dist anticorrelated --n 20000000
+    python -m paper_2107_09993_amd.learned train --dist independent      # -> nets/indep_d10.bin
+    python -m paper_2107_09993_amd.learned eval --dist independent --n 5000000
 """
 import argparse
 import json
@@ -18,6 +20,8 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_NET = os.path.join(HERE, "nets", "anti_d10.bin")
+# one trained network per training distribution
+NETS = {"anticorrelated": DEFAULT_NET, "independent": os.path.join(HERE, "nets", "indep_d10.bin")}
 
 
 def _soa(x, dev):
@@ -27,7 +31,7 @@ def _soa(x, dev):
 
 
 def train(d=10, n=1_000_000, datasets=64, first_seed=100, epochs=2, batch=65536, lr=2e-3,
-          feat_grid=4, seed=0, device="cuda", log=None):
+          feat_grid=4, seed=0, device="cuda", log=None, dist="anticorrelated"):
     """Train a fresh network; returns (mlp, summary dict)."""
     import torch
     import paper_2107_09993_amd as sky
@@ -40,7 +44,7 @@ def train(d=10, n=1_000_000, datasets=64, first_seed=100, epochs=2, batch=65536,
     t_train = 0.0
     points_trained = 0
     for s in range(first_seed, first_seed + datasets):
-        x = datagen.generate("anticorrelated", n, d, s)
+        x = datagen.generate(dist, n, d, s)
         xs = _soa(x, dev)
         idx = sky.compute(xs, layout="dn")
         cnt = torch.tensor([idx.numel()], dtype=torch.int32, device=dev)
@@ -58,14 +62,16 @@ def train(d=10, n=1_000_000, datasets=64, first_seed=100, epochs=2, batch=65536,
         losses.append(float(loss.item()))
         if log:
             log(json.dumps({"dataset_seed": s, "skyline_fraction": idx.numel() / n, "loss": losses[-1]}))
-    return mlp, {"datasets": datasets, "n": n, "d": d, "epochs": epochs, "batch": batch, "lr": lr,
+    return mlp, {"distribution": dist, "datasets": datasets, "n": n, "d": d, "epochs": epochs,
+                 "batch": batch, "lr": lr,
                  "feature_grid": feat_grid, "final_loss": losses[-1] if losses else None,
                  "first_loss": losses[0] if losses else None,
                  "train_points_per_s": points_trained / t_train if t_train > 0 else None}
 
 
-def evaluate(mlp, n=20_000_000, d=10, seed=0, k=4096, reps=3, device="cuda", x=None, log=None):
-    """Plain vs pivoted skyline timings and counters on one anti-correlated input."""
+def evaluate(mlp, n=20_000_000, d=10, seed=0, k=4096, reps=3, device="cuda", x=None, log=None,
+             dist="anticorrelated"):
+    """Plain vs pivoted skyline timings and counters on one input of `dist`."""
     import numpy as np
     import torch
     import paper_2107_09993_amd as sky
@@ -73,7 +79,7 @@ def evaluate(mlp, n=20_000_000, d=10, seed=0, k=4096, reps=3, device="cuda", x=N
 
     dev = torch.device(device)
     if x is None:
-        x = datagen.generate("anticorrelated", n, d, seed)
+        x = datagen.generate(dist, n, d, seed)
     xs = _soa(x, dev)
     g = sky.choose_grid(n, d)
 
@@ -101,7 +107,8 @@ def evaluate(mlp, n=20_000_000, d=10, seed=0, k=4096, reps=3, device="cuda", x=N
         return {"ms": ms, "pivot_removed": st["pivot_removed"], "survivor_points": st["survivor_points"],
                 "pair_tests": st["pair_tests"], "speedup_vs_plain": ms_plain / ms}
 
-    res = {"n": n, "d": d, "seed": seed, "grid_res": g, "k": k, "skyline": int(plain.numel()),
+    res = {"distribution": dist, "n": n, "d": d, "seed": seed, "grid_res": g, "k": k,
+           "skyline": int(plain.numel()),
            "identical_outputs": same,
            "plain": {"ms": ms_plain, "survivor_points": st_plain["survivor_points"],
                      "pair_tests": st_plain["pair_tests"]},
@@ -115,7 +122,8 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--out", default=DEFAULT_NET)
+    t.add_argument("--out", default=None)
+    t.add_argument("--dist", default="anticorrelated", choices=sorted(NETS))
     t.add_argument("--datasets", type=int, default=64)
     t.add_argument("--n", type=int, default=1_000_000)
     t.add_argument("--d", type=int, default=10)
@@ -123,21 +131,25 @@ def main():
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--feature-grid", type=int, default=4)
     e = sub.add_parser("eval")
-    e.add_argument("--net", default=DEFAULT_NET)
+    e.add_argument("--net", default=None)
+    e.add_argument("--dist", default="anticorrelated", choices=sorted(NETS))
     e.add_argument("--n", type=int, default=20_000_000)
     e.add_argument("--k", type=int, default=4096)
     a = ap.parse_args()
     import paper_2107_09993_amd as sky
     log = lambda s: print(s, flush=True)
     if a.cmd == "train":
+        out = a.out or NETS[a.dist]
         mlp, summary = train(d=a.d, n=a.n, datasets=a.datasets, epochs=a.epochs, lr=a.lr,
-                             feat_grid=a.feature_grid, log=log)
-        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
-        mlp.save(a.out)
-        log(json.dumps({"saved": a.out, **summary}))
+                             feat_grid=a.feature_grid, log=log, dist=a.dist)
+        os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+        mlp.save(out)
+        log(json.dumps({"saved": out, **summary}))
     else:
-        mlp = sky.MLP.load(a.net)
-        evaluate(mlp, n=a.n, d=mlp.d, k=a.k, log=log)
+        import torch
+        torch.zeros(1, device="cuda")  # bring up torch's device context before the library's calls
+        mlp = sky.MLP.load(a.net or NETS[a.dist])
+        evaluate(mlp, n=a.n, d=mlp.d, k=a.k, log=log, dist=a.dist)
 
 
 if __name__ == "__main__":

@@ -258,9 +258,12 @@ def test_compute_with_pivots(oracle_mod, name, dist, n, d, g, how, k):
     want = oracle.skyline_sfs(x)
     assert np.array_equal(got.cpu().numpy(), want)
     kk = min(k, n)
-    removed = surviving_mask(x, g) & L.dominated_by_any(x, x[piv[:kk]])
+    surv = surviving_mask(x, g)
+    removed = surv & L.dominated_by_any(x, x[piv[:kk]])
+    if not L.pivot_gate(x, surv, x[piv[:kk]]):
+        removed[:] = False  # the sampled removal rate is below the gate: no pre-filter pass
     assert st["pivot_removed"] == int(removed.sum())
-    assert st["survivor_points"] == int(surviving_mask(x, g).sum()) - int(removed.sum())
+    assert st["survivor_points"] == int(surv.sum()) - int(removed.sum())
 
 
 def test_pivot_index_out_of_range_is_reported():
