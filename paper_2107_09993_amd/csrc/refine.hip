@@ -102,9 +102,11 @@ static int refine_blocks_per_cu()
         int b = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_refine<D, M>, kRefineThreads, 0) != hipSuccess || b < 1)
             b = 1;
-        // SKYCELL_REFINE_BLOCKS caps the resident workgroups per CU (tuning sweeps)
+        // at most 4 resident workgroups per CU: more waves add L1/L2 misses
+        // faster than they hide latency (SKYCELL_REFINE_BLOCKS overrides the cap
+        // for tuning sweeps)
         const char *v = getenv("SKYCELL_REFINE_BLOCKS");
-        const int cap = v ? atoi(v) : 0;
+        const int cap = v ? atoi(v) : 4;
         if (cap >= 1 && cap < b) b = cap;
         blocks_per_cu = b;
     }
