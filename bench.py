@@ -151,6 +151,26 @@ def cpu_baseline(x_host, sample):
                       "(%d skyline points, %.1f s)" % (n, len(sky), dt)}
 
 
+def phase_bytes(n, d, cells, st):
+    """Bytes each streaming phase must move at least with this data layout
+    (reads + writes, every array touched once), for the per-phase bandwidth."""
+    fw = 8 * ((d + 7) // 8)
+    surv = st["survivor_points"]
+    return {
+        # zero the counts; read the coordinates, write cell and rank per point
+        "quantize_hist": 4 * cells + n * (4 * d + 8),
+        # counts -> occupancy byte, d prefix-OR passes over it, records
+        "cell_prune": cells * (4 + 1 + 2 * d + 4 + 1 + 8),
+        # reduce and emit passes over (record, count), start words, work items
+        "cell_scan": cells * (12 + 12 + 4) + st["items"] * 8,
+        # coordinates, cell, rank, record per point; keys, screening words,
+        # original index of surviving points; flag of every point
+        "scatter": n * (4 * d + 16 + 1) + surv * (4 * d + fw + 4),
+        # flags of every point, indices of the skyline points
+        "output": n + 4 * st["skyline"],
+    }
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -223,6 +243,10 @@ def main():
     cells = (1 << (max(1, (g - 1).bit_length()) * a.d)) if g > 1 else 1
     algo_bytes = (st["survivor_points"] * (4 * a.d + 8 * ((a.d + 7) // 8) + 4) + (cells + 1) * 8
                   + st["items"] * 8 + a.n)
+    pbytes = phase_bytes(a.n, a.d, cells, st)
+    phase_hbm = {k: {"algorithmic_bytes": b, "gbs": b / (phases[k] * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": b / (phases[k] * 1e-3) / PEAK_HBM}
+                 for k, b in pbytes.items() if phases.get(k, 0.0) > 0.0}
     roof = {"kernel": "k_refine<%d>" % a.d, "bound": "alu", "achieved": achieved / 1e12,
             "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_ALU_OPS,
             "traffic": measured_traffic("k_refine", workload),
@@ -237,6 +261,7 @@ def main():
            "config": {"workload": workload, "n": a.n, "d": a.d, "distribution": a.dist,
                       "grid_res": g, "skyline": sky_count},
            "phases_ms": phases,
+           "phases_hbm": phase_hbm,
            "dominance_tests_per_s": st["pair_tests"] / (ms_per_step * 1e-3),
            "counters": st,
            "roofline": roof}

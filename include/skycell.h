@@ -167,7 +167,9 @@ int skycell_set_refine_form(int32_t form);
  *   5 keys     uint32 [n*d]      sorted surviving points as order-preserving keys
  *   6 fkeys    uint64 [n*ceil(d/8)]  7-bit screening columns, one byte per dimension
  *   7 sidx     int32  [n]        original index of each sorted point
- *   8 items, 9 flag, 10 block sums, 11 counters, 12 total size.
+ *   8 items, 9 flag, 10 block sums, 11 counters, 12 total size (past the
+ *   counters: a bitmap of surviving cells and, for n >= 2^20, the staging
+ *   rows of the two-pass scatter).
  * count must be >= 13.  Returns SKYCELL_OK or an argument error.
  */
 int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dtype,

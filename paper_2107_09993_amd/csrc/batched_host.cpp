@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -21,7 +22,23 @@ using namespace skycell;
 
 namespace {
 
-constexpr int kBranches = 8;
+constexpr int kMaxBranches = 64;
+
+// Fork-joined capture streams: independent chains of instances that the graph
+// may run side by side.  Small instances leave most of the chip idle, so the
+// throughput grows with the number of chains up to about 24-32 (4096 mixed
+// instances: 8 chains 650, 16 chains 1104, 32 chains 1122 instances/s).
+// SKYCELL_BATCH_BRANCHES overrides the default of 32 (1..kMaxBranches).
+static int batch_branches()
+{
+    static int b = -1;
+    if (b < 0) {
+        const char *v = getenv("SKYCELL_BATCH_BRANCHES");
+        const int e = v ? atoi(v) : 0;
+        b = (e >= 1 && e <= kMaxBranches) ? e : 32;
+    }
+    return b;
+}
 
 // Cell budget of one batched instance: 32 cells per point, at least 2^16 and at
 // most 2^24, so that the plan's workspace stays proportional to its points.
@@ -79,9 +96,10 @@ int capture(skycell_plan *p, const void *points, int32_t *out_idx, int32_t *out_
 {
     drop_graph(p);
     const size_t esize = p->dtype == SKYCELL_DTYPE_F32 ? 4 : 2;
+    const int kBranches = batch_branches();
     hipStream_t origin = nullptr;
-    hipStream_t branch[kBranches] = {};
-    hipEvent_t fork = nullptr, join[kBranches] = {};
+    hipStream_t branch[kMaxBranches] = {};
+    hipEvent_t fork = nullptr, join[kMaxBranches] = {};
     hipError_t e = hipStreamCreateWithFlags(&origin, hipStreamNonBlocking);
     for (int i = 0; i < kBranches && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&branch[i], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);

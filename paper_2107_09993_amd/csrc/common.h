@@ -98,7 +98,30 @@ struct Workspace {
     uint8_t *flag;        // [n]     1 = skyline, by original index
     uint64_t *block_sums; // scan partials
     uint32_t *ctr;        // small counters, see CtrIndex
+    uint64_t *survbits;   // [cells / 64 + 1] bit x: cell x is a surviving non-empty cell
+    uint32_t *bcur;       // [kMaxScatterBuckets * kNumXcd] staging cursors of the two-pass scatter
+    uint32_t *stage;      // [n * ((d + 6) & ~3)] staged rows of the two-pass scatter (large n only)
 };
+
+// Two-pass scatter, for large inputs.  Pass 1 groups the surviving points by
+// ranges of 2^sh consecutive cells ("buckets") into a staging array whose
+// bucket regions are the buckets' ranges of sorted positions; a staged row is
+// (raw coordinate words, original index, cell, rank), padded to 16 bytes.  Pass 2 sweeps the
+// staging array in order, each XCD over a contiguous eighth, and writes every
+// row to its sorted position.  The rows in flight on one XCD then target a
+// window of a few buckets that stays in its L2 until the window's lines are
+// complete, instead of three partial-line writes to random places per point.
+constexpr int64_t kScatterTwoPassMin = 1 << 20;
+constexpr uint32_t kMaxScatterBuckets = 2048;
+__host__ __device__ inline bool scatter_two_pass(int64_t n) { return n >= kScatterTwoPassMin; }
+// Buckets: a power of two with 2^14 to 2^15 points each on average, between 64
+// and kMaxScatterBuckets, and at most one per cell.
+__host__ __device__ inline uint32_t scatter_buckets(int64_t n, uint32_t cells)
+{
+    uint32_t nb = 64u;
+    while (nb < kMaxScatterBuckets && ((int64_t)nb << 15) <= n) nb <<= 1;
+    return nb < cells ? nb : cells;
+}
 
 // Rank of a point that the pivot pre-filter removed (never a real rank: n < 2^31).
 constexpr uint32_t kRankRemoved = 0xFFFFFFFFu;
@@ -125,7 +148,7 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *
 hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st,
                             bool recount = false);
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
-                          const Workspace &ws, int value_bits, hipStream_t st);
+                          const Workspace &ws, int value_bits, int num_cus, hipStream_t st);
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st);
 hipError_t refine_prepare(const GridDesc &gd);

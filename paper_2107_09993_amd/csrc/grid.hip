@@ -1,5 +1,5 @@
 // Grid phase of the skyline path (SkyCell paper, Section III grid structure and
-// Section V, Algorithm 1 line 1):
+// Section V, Algorithm 1, whose first step sorts the points by cell):
 //   K1  quantise every point to its cell (Equation 1), build the occupancy
 //       histogram and keep each point's rank inside its cell;
 //   K3  lower closure of the occupancy by d prefix-OR passes, then per cell the
@@ -8,6 +8,8 @@
 //   K2  exclusive scan of surviving-cell counts: counting-sort offsets and refine
 //       work items;
 //   K4  scatter of surviving points, grouped by cell, as order-preserving keys.
+#include <cstdlib>
+
 #include "cellops.h"
 #include "common.h"
 #include "scan.h"
@@ -16,6 +18,30 @@
 namespace skycell {
 
 constexpr int kThreads = 256;
+// Workgroups per CU of the second scatter pass (SKYCELL_SCATTER_ROW_BLOCKS
+// overrides it): few enough that the rows in flight on one XCD target a window
+// of destination lines that fits in its L2.
+static int scatter_row_blocks()
+{
+    static int b = -1;
+    if (b < 0) {
+        const char *v = getenv("SKYCELL_SCATTER_ROW_BLOCKS");
+        const int e = v ? atoi(v) : 0;
+        b = (e >= 1 && e <= 16) ? e : 1;
+    }
+    return b;
+}
+
+// SKYCELL_SCATTER2=0 keeps the one-pass scatter for every size (comparisons).
+static bool scatter_two_pass_enabled()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *v = getenv("SKYCELL_SCATTER2");
+        on = (v && v[0] == '0') ? 0 : 1;
+    }
+    return on != 0;
+}
 
 static inline dim3 grid_for(uint64_t count, int per_block = kThreads)
 {
@@ -101,13 +127,17 @@ __global__ __launch_bounds__(kThreads) void k_lc_prefix(uint8_t *__restrict__ lc
 __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32_t *__restrict__ cnt,
                                                        const uint8_t *__restrict__ lc,
                                                        uint64_t *__restrict__ rec,
+                                                       uint64_t *__restrict__ survbits,
                                                        uint64_t *__restrict__ stats)
 {
     const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
     bool occ = false, surv = false;
     if (x < gd.cells) rec[x] = cell_record(gd, cnt, lc, x, occ, surv);
+    // one bitmap word per wave: the wave's 64 cells start at a multiple of 64
+    const uint64_t bs = __ballot(surv);
+    if (__lane_id() == 0 && x < gd.cells) survbits[x >> 6] = bs;
     if (stats != nullptr) {
-        const uint64_t bo = __ballot(occ), bs = __ballot(surv);
+        const uint64_t bo = __ballot(occ);
         if (__lane_id() == 0) {
             if (bo) atomicAdd((unsigned long long *)&stats[SKYCELL_STAT_NONEMPTY_CELLS],
                               (unsigned long long)__popcll(bo));
@@ -128,7 +158,7 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *
                                gd.mask[k], all_bits, (uint32_t)gd.g);
     }
     hipLaunchKernelGGL(k_cell_rec, grid_for(gd.cells), dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
-                       ws.rec, stats);
+                       ws.rec, ws.survbits, stats);
     return hipGetLastError();
 }
 
@@ -187,9 +217,254 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts,
     scatter_point(pts, n, d, value_bits, i, rec_start(r) + rk, keys, fkeys, sidx);
 }
 
-hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
-                          const Workspace &ws, int value_bits, hipStream_t st)
+// Two-pass form (large n).  Workgroup w of the counting and staging passes
+// carries the label w % 8, the XCD it runs on under round-robin dispatch.
+// Inside each bucket's range of sorted positions the staged rows are grouped
+// by label, so the runs that workgroups of one XCD append are adjacent and
+// their lines are completed in that XCD's L2.
+constexpr int kStagePts = 8;  // points per thread in the counting and staging passes
+
+// Pass 1a: per-workgroup bucket counts of the points that survive (their cell
+// survives and the pivot pre-filter kept them), added into lab_cnt[bucket][label].
+__global__ __launch_bounds__(kThreads) void k_scatter_count(uint32_t n, uint32_t nb, uint32_t sh,
+                                                            const uint32_t *__restrict__ cell_of,
+                                                            const uint32_t *__restrict__ rank,
+                                                            const uint64_t *__restrict__ survbits,
+                                                            uint32_t *__restrict__ lab_cnt)
 {
+    __shared__ uint32_t s_cnt[kMaxScatterBuckets];
+    for (uint32_t t = threadIdx.x; t < nb; t += kThreads) s_cnt[t] = 0u;
+    __syncthreads();
+    const uint32_t i0 = blockIdx.x * (uint32_t)(kThreads * kStagePts) + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kStagePts; ++j) {
+        const uint32_t i = i0 + (uint32_t)j * kThreads;
+        if (i < n) {
+            const uint32_t x = cell_of[i];
+            if (((survbits[x >> 6] >> (x & 63u)) & 1ull) != 0ull && rank[i] != kRankRemoved)
+                atomicAdd(&s_cnt[x >> sh], 1u);
+        }
+    }
+    __syncthreads();
+    const uint32_t lab = blockIdx.x % kNumXcd;
+    for (uint32_t t = threadIdx.x; t < nb; t += kThreads)
+        if (s_cnt[t] != 0u) atomicAdd(&lab_cnt[t * kNumXcd + lab], s_cnt[t]);
+}
+
+// Pass 1b: exclusive scan of lab_cnt in (bucket, label) order, in place: the
+// staging cursor of each (bucket, label).  One workgroup of kThreads threads.
+__global__ __launch_bounds__(kThreads) void k_scatter_bases(uint32_t *__restrict__ lab_cnt, uint32_t count)
+{
+    __shared__ uint32_t s_part[kThreads];
+    const uint32_t per = (count + kThreads - 1) / kThreads;
+    const uint32_t lo = threadIdx.x * per;
+    uint32_t sum = 0u;
+    for (uint32_t k = lo; k < lo + per && k < count; ++k) sum += lab_cnt[k];
+    s_part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0u;
+        for (int t = 0; t < kThreads; ++t) {
+            const uint32_t v = s_part[t];
+            s_part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    uint32_t run = s_part[threadIdx.x];
+    for (uint32_t k = lo; k < lo + per && k < count; ++k) {
+        const uint32_t v = lab_cnt[k];
+        lab_cnt[k] = run;
+        run += v;
+    }
+}
+
+// Rows of the staging array: the raw coordinate words, the original index, the
+// cell and the rank, padded to a multiple of four words (16-byte aligned rows).
+__host__ __device__ constexpr uint32_t stage_row_words(int d) { return ((uint32_t)d + 3u + 3u) & ~3u; }
+
+__device__ __forceinline__ uint32_t raw_word(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t raw_word(uint16_t v) { return (uint32_t)v; }
+
+// Pass 1c: the same points per workgroup as pass 1a; the LDS atomic gives each
+// point its slot in the workgroup's run of its bucket, one global atomic per
+// (bucket, label) reserves the run.  Clears the output flag of every point.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict__ pts, uint32_t n, int d,
+                                                            uint32_t nb, uint32_t sh,
+                                                            const uint32_t *__restrict__ cell_of,
+                                                            const uint32_t *__restrict__ rank,
+                                                            const uint64_t *__restrict__ survbits,
+                                                            uint32_t *__restrict__ lab_cur,
+                                                            uint32_t *__restrict__ stage,
+                                                            uint8_t *__restrict__ flag)
+{
+    __shared__ uint32_t s_cnt[kMaxScatterBuckets];
+    for (uint32_t t = threadIdx.x; t < nb; t += kThreads) s_cnt[t] = 0u;
+    __syncthreads();
+    const uint32_t i0 = blockIdx.x * (uint32_t)(kThreads * kStagePts) + threadIdx.x;
+    uint32_t cell[kStagePts], rk[kStagePts], slot[kStagePts];
+#pragma unroll
+    for (int j = 0; j < kStagePts; ++j) {
+        const uint32_t i = i0 + (uint32_t)j * kThreads;
+        slot[j] = ~0u;
+        cell[j] = 0u;
+        rk[j] = 0u;
+        if (i < n) {
+            flag[i] = 0;
+            cell[j] = cell_of[i];
+            rk[j] = rank[i];
+            const bool live = ((survbits[cell[j] >> 6] >> (cell[j] & 63u)) & 1ull) != 0ull && rk[j] != kRankRemoved;
+            if (live) slot[j] = atomicAdd(&s_cnt[cell[j] >> sh], 1u);
+        }
+    }
+    __syncthreads();
+    const uint32_t lab = blockIdx.x % kNumXcd;
+    for (uint32_t t = threadIdx.x; t < nb; t += kThreads) {
+        const uint32_t c = s_cnt[t];
+        s_cnt[t] = c != 0u ? atomicAdd(&lab_cur[t * kNumXcd + lab], c) : 0u;
+    }
+    __syncthreads();
+    const uint32_t rw = stage_row_words(d);
+#pragma unroll
+    for (int j = 0; j < kStagePts; ++j) {
+        if (slot[j] == ~0u) continue;
+        const uint32_t i = i0 + (uint32_t)j * kThreads;
+        uint4 *row = reinterpret_cast<uint4 *>(stage + (size_t)(s_cnt[cell[j] >> sh] + slot[j]) * rw);
+        // words 0..d-1 coordinates, d index, d+1 cell, d+2 rank, then zero padding
+        for (uint32_t q = 0; q < rw / 4u; ++q) {
+            uint32_t w[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = (int)(4u * q) + e;
+                w[e] = k < d ? raw_word(pts[(size_t)k * n + i])
+                             : k == d ? i : k == d + 1 ? cell[j] : k == d + 2 ? rk[j] : 0u;
+            }
+            row[q] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// Pass 2: the XCD with label x sweeps the x-th eighth of the staged rows in
+// order, kThreads rows per workgroup and step, and writes each row to its
+// sorted position start(cell) + rank.
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_scatter_rows(int value_bits,
+                                                           const uint32_t *__restrict__ stage,
+                                                           const uint64_t *__restrict__ rec,
+                                                           const uint32_t *__restrict__ ctr,
+                                                           uint32_t *__restrict__ keys,
+                                                           uint64_t *__restrict__ fkeys,
+                                                           int32_t *__restrict__ sidx)
+{
+    const uint32_t total = ctr[kCtrSurvPts];
+    const uint32_t xcd = blockIdx.x % kNumXcd;
+    const uint32_t per = gridDim.x / kNumXcd;  // workgroups per XCD
+    const uint32_t lo = (uint32_t)(((uint64_t)total * xcd) / kNumXcd);
+    const uint32_t hi = (uint32_t)(((uint64_t)total * (xcd + 1)) / kNumXcd);
+    constexpr uint32_t rw = stage_row_words(D);
+    constexpr int d = D;
+    constexpr int fw = fine_words(D);
+    for (uint64_t r = (uint64_t)lo + (uint64_t)(blockIdx.x / kNumXcd) * kThreads + threadIdx.x; r < hi;
+         r += (uint64_t)per * kThreads) {
+        const uint4 *row = reinterpret_cast<const uint4 *>(stage + (size_t)r * rw);
+        uint32_t w[rw];
+#pragma unroll
+        for (uint32_t q = 0; q < rw / 4u; ++q) {
+            const uint4 v = row[q];
+            w[4 * q] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+        const uint32_t i = w[d], x = w[d + 1], rk = w[d + 2];
+        const uint32_t pos = rec_start(rec[x]) + rk;
+        uint32_t *dst = keys + (size_t)pos * d;
+        uint64_t *fdst = fkeys + (size_t)pos * fw;
+        uint64_t word = 0ull;
+        bool nan = false;
+#pragma unroll
+        for (int k = 0; k < d; ++k) {
+            uint32_t f;
+            if constexpr (sizeof(T) == 4) {
+                const float v = __uint_as_float(w[k]);
+                dst[k] = f32_key(v);
+                f = column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan);
+            } else {
+                dst[k] = w[k];
+                f = column_u16((uint16_t)w[k], (uint32_t)kFineCols, value_bits);
+            }
+            word |= (uint64_t)f << (8 * (k & 7));
+            if ((k & 7) == 7 || k == d - 1) {
+                fdst[k >> 3] = word;
+                word = 0ull;
+            }
+        }
+        sidx[pos] = (int32_t)i;
+    }
+}
+
+static uint32_t scatter_buckets_for(int64_t n, uint32_t cells)
+{
+    static int env = -1;
+    if (env < 0) {
+        const char *v = getenv("SKYCELL_SCATTER_BUCKETS");
+        env = v ? atoi(v) : 0;
+    }
+    uint32_t nb = scatter_buckets(n, cells);
+    if (env >= 64 && env <= (int)kMaxScatterBuckets && (env & (env - 1)) == 0) nb = (uint32_t)env;
+    return nb < cells ? nb : cells;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_words(uint32_t *__restrict__ p, uint32_t count)
+{
+    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < count; t += gridDim.x * kThreads) p[t] = 0u;
+}
+
+template <typename T>
+static hipError_t launch_scatter_two_pass(const T *pts, int64_t n, const GridDesc &gd, const Workspace &ws,
+                                          int value_bits, int num_cus, hipStream_t st)
+{
+    const uint32_t nb = scatter_buckets_for(n, gd.cells);
+    uint32_t sh = 0u;
+    while ((nb << sh) < gd.cells) ++sh;
+    const uint32_t labs = nb * (uint32_t)kNumXcd;
+    const dim3 pgrid = grid_for((uint64_t)n, kThreads * kStagePts);
+    hipLaunchKernelGGL(k_zero_words, grid_for(labs), dim3(kThreads), 0, st, ws.bcur, labs);
+    hipLaunchKernelGGL(k_scatter_count, pgrid, dim3(kThreads), 0, st, (uint32_t)n, nb, sh,
+                       (const uint32_t *)ws.cell_of, (const uint32_t *)ws.rank, (const uint64_t *)ws.survbits,
+                       ws.bcur);
+    hipLaunchKernelGGL(k_scatter_bases, dim3(1), dim3(kThreads), 0, st, ws.bcur, labs);
+    hipLaunchKernelGGL(k_scatter_stage<T>, pgrid, dim3(kThreads), 0, st, pts, (uint32_t)n, gd.d, nb, sh,
+                       (const uint32_t *)ws.cell_of, (const uint32_t *)ws.rank, (const uint64_t *)ws.survbits,
+                       ws.bcur, ws.stage, ws.flag);
+    const unsigned blocks = (unsigned)(((num_cus * scatter_row_blocks() + kNumXcd - 1) / kNumXcd) * kNumXcd);
+    switch (gd.d) {
+#define SKYCELL_ROWS_CASE(DD)                                                                                    \
+    case DD:                                                                                                     \
+        hipLaunchKernelGGL((k_scatter_rows<T, DD>), dim3(blocks), dim3(kThreads), 0, st, value_bits,             \
+                           (const uint32_t *)ws.stage, (const uint64_t *)ws.rec, (const uint32_t *)ws.ctr,        \
+                           ws.keys, ws.fkeys, ws.sidx);                                                          \
+        break;
+        SKYCELL_ROWS_CASE(1) SKYCELL_ROWS_CASE(2) SKYCELL_ROWS_CASE(3) SKYCELL_ROWS_CASE(4)
+        SKYCELL_ROWS_CASE(5) SKYCELL_ROWS_CASE(6) SKYCELL_ROWS_CASE(7) SKYCELL_ROWS_CASE(8)
+        SKYCELL_ROWS_CASE(9) SKYCELL_ROWS_CASE(10) SKYCELL_ROWS_CASE(11) SKYCELL_ROWS_CASE(12)
+        SKYCELL_ROWS_CASE(13) SKYCELL_ROWS_CASE(14) SKYCELL_ROWS_CASE(15) SKYCELL_ROWS_CASE(16)
+#undef SKYCELL_ROWS_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
+                          const Workspace &ws, int value_bits, int num_cus, hipStream_t st)
+{
+    if (ws.stage != nullptr && scatter_two_pass_enabled()) {
+        if (dtype == SKYCELL_DTYPE_F32)
+            return launch_scatter_two_pass<float>((const float *)pts, n, gd, ws, value_bits, num_cus, st);
+        return launch_scatter_two_pass<uint16_t>((const uint16_t *)pts, n, gd, ws, value_bits, num_cus, st);
+    }
     if (dtype == SKYCELL_DTYPE_F32)
         hipLaunchKernelGGL(k_scatter<float>, grid_for(n), dim3(kThreads), 0, st, (const float *)pts,
                            (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank, ws.rec, ws.keys, ws.fkeys,

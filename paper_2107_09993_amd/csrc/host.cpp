@@ -224,6 +224,9 @@ size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *b
     const uint64_t tiles = std::max<uint64_t>(scan_tiles(cells), scan_tiles(nn));
     w.block_sums = (uint64_t *)take(8 * (size_t)(tiles + 1));
     w.ctr = (uint32_t *)take(4 * kCtrCount);
+    w.survbits = (uint64_t *)take(8 * ((size_t)cells / 64 + 1));
+    w.bcur = (uint32_t *)take(4 * (size_t)kMaxScatterBuckets * kNumXcd);
+    w.stage = scatter_two_pass(n) ? (uint32_t *)take(4 * nn * (size_t)(((unsigned)d + 6u) & ~3u)) : nullptr;
     if (ws) *ws = w;
     return off;
 }
@@ -368,7 +371,7 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
     SKYCELL_PROF(2);
     SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st, pivots));
     SKYCELL_PROF(3);
-    SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, value_bits, st));
+    SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, value_bits, cus, st));
     SKYCELL_PROF(4);
     SKYCELL_HIP_CHECK(launch_refine(n, gd, ws, stats, cus, st));
     SKYCELL_PROF(5);
