@@ -93,6 +93,10 @@ def _check_sorted_arrays(x, g, ws, offs, st, value_bits=10):
     (TWO_PASS_MIN, 5, 8, "independent"),        # exactly at the threshold
     (1_300_001, 6, 6, "independent"),           # ragged n, non-power-of-two grid
     (1_100_003, 5, 2, "correlated"),            # 32 cells: fewer cells than buckets
+    (TWO_PASS_MIN + 5, 16, 2, "correlated"),    # widest rows (d = 16)
+    (TWO_PASS_MIN + 5, 1, 64, "independent"),   # narrowest rows, one skyline point
+    (TWO_PASS_MIN + 5, 2, 32, "independent"),
+    (TWO_PASS_MIN + 5, 3, 16, "anticorrelated"),
 ])
 def test_sorted_arrays_f32(oracle_mod, n, d, g, dist):
     x = datagen.generate(dist, n, d, seed=11)
