@@ -66,27 +66,50 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Loader ld, uint64_
 // In-place exclusive scan of `nb` tile sums; block_sums[nb] receives the total.
 __global__ __launch_bounds__(kPartialThreads) void k_scan_partials(uint64_t *block_sums, uint32_t nb);
 
+// Rescan of one tile: values are loaded lane-contiguous (coalesced) into LDS,
+// each thread scans its own run of kScanPer consecutive elements there and
+// overwrites them with their exclusive prefixes (the element after the tile
+// gets the tile's end), and the emitter is then called lane-contiguous with
+// prefix p[e] and value p[e+1] - p[e], so its per-element writes coalesce.
 template <typename T, typename Loader, typename Emitter>
 __global__ __launch_bounds__(kScanThreads) void k_scan_emit(Loader ld, Emitter em, uint64_t count,
                                                             const uint64_t *block_sums)
 {
     __shared__ T s_w[kScanThreads / kWave];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+    __shared__ T s_v[kScanTile + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int e = j * kScanThreads + (int)threadIdx.x;
+        const uint64_t i = base + (uint64_t)e;
+        s_v[e] = (i < count) ? ld(i) : T(0);
+    }
+    __syncthreads();
+    const int own = (int)threadIdx.x * kScanPer;
     T v[kScanPer];
     T s = 0;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-        const uint64_t i = base + j;
-        v[j] = (i < count) ? ld(i) : T(0);
+        v[j] = s_v[own + j];
         s += v[j];
     }
     T tot;
     T run = block_exclusive_scan<T, kScanThreads>(s, &tot, s_w) + (T)block_sums[blockIdx.x];
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-        const uint64_t i = base + j;
-        if (i < count) em(i, run, v[j]);
+        s_v[own + j] = run;
         run += v[j];
+    }
+    if (threadIdx.x == kScanThreads - 1) s_v[kScanTile] = run;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int e = j * kScanThreads + (int)threadIdx.x;
+        const uint64_t i = base + (uint64_t)e;
+        if (i < count) {
+            const T p = s_v[e];
+            em(i, p, (T)(s_v[e + 1] - p));
+        }
     }
 }
 
