@@ -247,9 +247,12 @@ def main():
     phase_hbm = {k: {"algorithmic_bytes": b, "gbs": b / (phases[k] * 1e-3) / 1e9,
                      "frac_of_hbm_peak": b / (phases[k] * 1e-3) / PEAK_HBM}
                  for k, b in pbytes.items() if phases.get(k, 0.0) > 0.0}
+    traffic = measured_traffic("k_refine", workload)
     roof = {"kernel": "k_refine<%d>" % a.d, "bound": "alu", "achieved": achieved / 1e12,
             "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_ALU_OPS,
-            "traffic": measured_traffic("k_refine", workload),
+            "traffic": traffic,
+            # measured bytes per launch / launch time (rocprofv3 FETCH_SIZE + WRITE_SIZE)
+            "traffic_gbs": traffic / (refine_ms * 1e-3) / 1e9 if traffic else None,
             "algorithmic_bytes": algo_bytes,
             "work": "%d candidate-vs-query domination tests x %d compares per launch"
                     % (st["pair_tests"], a.d),

@@ -55,10 +55,26 @@ __device__ __forceinline__ void lc_prefix_line(uint8_t *__restrict__ lc, uint32_
 {
     uint32_t x = deposit_bits(t, all_bits & ~m);
     uint8_t v = 0;
-    for (uint32_t j = 0; j < g; ++j) {
-        v |= lc[x];
-        lc[x] = v;
-        if (j + 1 < g) x = morton_inc(x, m);
+    // eight columns at a time: all loads of a chunk are issued before its stores
+    constexpr uint32_t kChunk = 8;
+    for (uint32_t j0 = 0; j0 < g; j0 += kChunk) {
+        const uint32_t len = g - j0 < kChunk ? g - j0 : kChunk;
+        uint32_t xs[kChunk];
+        uint8_t f[kChunk];
+#pragma unroll
+        for (uint32_t u = 0; u < kChunk; ++u) {
+            xs[u] = x;
+            f[u] = u < len ? lc[x] : (uint8_t)0;
+            if (u + 1 < len) x = morton_inc(x, m);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kChunk; ++u) {
+            if (u < len) {
+                v |= f[u];
+                lc[xs[u]] = v;
+            }
+        }
+        if (j0 + kChunk < g) x = morton_inc(x, m);
     }
 }
 

@@ -106,3 +106,23 @@ def test_graph_batched_workload_shapes_sampled(oracle_mod):
             idx = rng.integers(0, n, size=40)
             assert np.array_equal(oracle_mod.is_skyline(a, idx), flag[idx]), "instance %d" % b
     plan.close()
+
+
+def test_graph_batched_merge_law(oracle_mod):
+    """sky(A1 u ... u A8) = sky(sky(A1) u ... u sky(A8)): the parts' skylines from
+    one batched launch, merged and reduced by the single-instance path, give the
+    skyline of the whole input (and the oracle's)."""
+    dev = _dev()
+    x = datagen.anticorrelated(60_000, 5, seed=31)
+    cuts = np.sort(np.random.default_rng(31).choice(np.arange(1, len(x)), 7, replace=False))
+    parts = np.split(np.arange(len(x)), cuts)
+    plan = sky.BatchedPlan([len(p) for p in parts], [5] * len(parts), device=dev)
+    plan.run(plan.pack([np.ascontiguousarray(x[p]) for p in parts]))
+    kept = np.concatenate([p[r] for p, r in zip(parts, plan.results())])
+    plan.close()
+    merged = torch.from_numpy(np.ascontiguousarray(x[kept].T)).to(dev)
+    again = kept[sky.compute(merged, layout="dn").cpu().numpy()]
+    whole = sky.compute(torch.from_numpy(np.ascontiguousarray(x.T)).to(dev), layout="dn").cpu().numpy()
+    ref = oracle_mod.skyline_sfs(x)
+    assert np.array_equal(np.sort(again), ref)
+    assert np.array_equal(whole, ref)
