@@ -131,8 +131,9 @@ int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d,
 int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res);
 
 /*
- * Load an autotuner table (text, one "d log2n dtype g [form]" line per entry,
- * form 0 = lane, 1 = wave refine, see skycell_set_refine_form; '#' starts a
+ * Load an autotuner table (text, one "d log2n dtype g [form [parts]]" line per
+ * entry, form 0 = lane, 1 = wave refine, see skycell_set_refine_form; parts
+ * the wave form's waves per item, see skycell_set_wave_parts; '#' starts a
  * comment line).  dtype is SKYCELL_DTYPE_* for single calls and
  * SKYCELL_DTYPE_* + 2 for the instances of a batched plan.  NULL clears the
  * table.  Applies to all later calls in the process.  The Python binding loads
@@ -150,6 +151,17 @@ int skycell_load_tuning(const char *path);
  * SKYCELL_REFINE_FORM=lane|wave in the environment sets it at the first call.
  */
 int skycell_set_refine_form(int32_t form);
+
+/*
+ * Waves per work item of the wave form for all later calls in the process:
+ * 0 = chosen per call (the tuning table's parts column for the call's d, n and
+ * grid, else 1), 1..64 = that many.  With p parts, p waves walk the same item's
+ * lower cone and each screens every p-th group of its candidates, so a cone
+ * that holds most of the input is shared by p waves instead of one.  The
+ * result never depends on it.  Returns SKYCELL_E_INVAL outside [0, 64].
+ * SKYCELL_WAVE_PARTS in the environment sets it at the first call.
+ */
+int skycell_set_wave_parts(int32_t parts);
 
 /*
  * Byte offsets of the workspace's sub-buffers for (n, d, grid_res) (grid_res 0 =

@@ -57,6 +57,7 @@ def lib():
     L.skycell_choose_grid.argtypes = [i64, i32, i32, ctypes.POINTER(i32)]
     L.skycell_load_tuning.argtypes = [ctypes.c_char_p]
     L.skycell_set_refine_form.argtypes = [i32]
+    L.skycell_set_wave_parts.argtypes = [i32]
     L.skycell_workspace_layout.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz), i32]
     L.skycell_profile_enable.argtypes = [i32]
     L.skycell_profile_read.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
@@ -85,6 +86,7 @@ def lib():
     L.skycell_last_error.restype = ctypes.c_char_p
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
                  "skycell_compute_ws", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
+                 "skycell_set_wave_parts",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
                  "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
                  "skycell_plan_destroy", "skycell_mlp_num_params", "skycell_mlp_create",
@@ -149,6 +151,11 @@ REFINE_FORMS = {"auto": -1, "lane": 0, "wave": 1}
 def set_refine_form(form):
     """Refine form for later calls: "auto" (per call), "lane" or "wave"."""
     _check(lib().skycell_set_refine_form(REFINE_FORMS[form]))
+
+
+def set_wave_parts(parts):
+    """Waves per work item of the wave-form refine for later calls (0 = per call)."""
+    _check(lib().skycell_set_wave_parts(int(parts)))
 
 
 def load_tuning(path):

@@ -1,11 +1,13 @@
 """Autotuner for the grid resolution (cells per dimension) of the skyline path.
 
 For every (d, n) on a grid of shapes it times the single-instance path on the
-three synthetic distributions for each candidate grid and refine form and
-keeps, per (d, n), the pair with the lowest mean time (the distribution of a future input is not
-known when the grid is chosen).  The result is a text table of
-"d log2n dtype g form" lines that the library loads with skycell_load_tuning
-(form: the refine form, 0 lane, 1 wave):
+three synthetic distributions for each candidate grid, refine form and (for the
+wave form) number of waves per work item, and keeps, per (d, n), the choice
+with the lowest mean time (the distribution of a future input is not known
+when the grid is chosen).  The result is a text table of
+"d log2n dtype g form parts" lines that the library loads with
+skycell_load_tuning (form: the refine form, 0 lane, 1 wave; parts: waves per
+item of the wave form):
 
     dtype 0 = binary32, single-instance calls (skycell_compute with grid_res 0)
     dtype 2 = binary32, instances of a batched plan
@@ -49,6 +51,7 @@ def time_once(sky, torch, soa, n, d, g, reps):
 
 
 FORMS = ("lane", "wave")
+WAVE_PARTS = (1, 2, 4, 8, 16)
 
 
 def sweep(dims, sizes, reps=2, log=print):
@@ -65,33 +68,35 @@ def sweep(dims, sizes, reps=2, log=print):
             # single calls up to the library's 2^24-cell default budget
             max_cells = min(1 << 24, max(1 << 16, 32 * n))
             grids = candidate_grids(n, d, max_cells)
-            configs = [(g, f) for g in grids for f in FORMS]
+            configs = [(g, "lane", 1) for g in grids] + [(g, "wave", p) for g in grids for p in WAVE_PARTS]
             totals = dict.fromkeys(configs, 0.0)
             for k, dist in enumerate(datagen.DISTRIBUTIONS):
                 x = datagen.generate(dist, n, d, seed=100 + k)
                 soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
-                for g, f in configs:
+                for g, f, p in configs:
                     sky.set_refine_form(f)
-                    totals[(g, f)] += time_once(sky, torch, soa, n, d, g, reps)
+                    sky.set_wave_parts(p)
+                    totals[(g, f, p)] += time_once(sky, torch, soa, n, d, g, reps)
                 del soa
             sky.set_refine_form("auto")
+            sky.set_wave_parts(0)
             best = min(configs, key=lambda c: totals[c])
             l2 = int(round(math.log2(n)))
-            table.append((d, l2, best[0], FORMS.index(best[1])))
-            log(json.dumps({"d": d, "n": n, "best": "%d/%s" % best,
-                            "mean_ms": {"%d/%s" % c: round(1e3 * t / 3, 3) for c, t in totals.items()}}))
+            table.append((d, l2, best[0], FORMS.index(best[1]), best[2]))
+            log(json.dumps({"d": d, "n": n, "best": "%d/%s/%d" % best,
+                            "mean_ms": {"%d/%s/%d" % c: round(1e3 * t / 3, 3) for c, t in totals.items()}}))
     return table
 
 
 def write_table(table, path):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
-        f.write("# d log2n dtype g form  -- grid resolution and refine form (0 lane, 1 wave) with the\n")
-        f.write("# lowest mean time over the independent, correlated and anti-correlated inputs\n")
-        f.write("# (paper_2107_09993_amd.autotune)\n")
-        for d, l2, g, form in table:
-            f.write("%d %d 0 %d %d\n" % (d, l2, g, form))
-            f.write("%d %d 2 %d %d\n" % (d, l2, g, form))
+        f.write("# d log2n dtype g form parts  -- grid resolution, refine form (0 lane, 1 wave) and\n")
+        f.write("# waves per item of the wave form with the lowest mean time over the independent,\n")
+        f.write("# correlated and anti-correlated inputs (paper_2107_09993_amd.autotune)\n")
+        for d, l2, g, form, parts in table:
+            f.write("%d %d 0 %d %d %d\n" % (d, l2, g, form, parts))
+            f.write("%d %d 2 %d %d %d\n" % (d, l2, g, form, parts))
 
 
 def main():

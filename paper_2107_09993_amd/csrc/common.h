@@ -42,6 +42,7 @@ __host__ __device__ constexpr int items_per_group(int) { return 2; }
 // of one cell; the item's count field has 6 bits).  GridDesc::m takes this
 // value when a call uses the wave form.
 constexpr int kWaveItemPoints = 63;
+constexpr int kMaxWaveParts = 64;
 
 // Number of XCDs (each with its own L2) that workgroups are spread over
 // round-robin; the refine gives each one a contiguous share of the work.
@@ -60,6 +61,7 @@ struct GridDesc {
     uint32_t cells;            // 2^(r*d): size of the index space
     uint32_t mask[kMaxD];      // index bits that hold dimension k
     int32_t m;                 // query points per refine work item (1, 2 or 4)
+    int32_t parts;             // wave form: waves that share one item's cone (>= 1)
 };
 
 // Index of the cell one column lower / higher in the dimension whose bits are

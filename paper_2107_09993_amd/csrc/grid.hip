@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts,
                                                       uint32_t *__restrict__ keys,
                                                       uint64_t *__restrict__ fkeys,
                                                       int32_t *__restrict__ sidx,
-                                                      uint8_t *__restrict__ flag)
+                                                      uint8_t *__restrict__ flag, uint8_t live_flag)
 {
     const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
@@ -214,8 +214,15 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts,
     if (!rec_surv(r)) return;
     const uint32_t rk = rank[i];
     if (rk == kRankRemoved) return;
+    if (live_flag) flag[i] = live_flag;
     scatter_point(pts, n, d, value_bits, i, rec_start(r) + rk, keys, fkeys, sidx);
 }
+
+// Output flag the scatter gives each surviving point: the lane form of the
+// refine sets the flags of skyline points itself (start 0), the wave form
+// clears the flags of dominated points (start 1), because several waves may
+// share one point's cone there.
+static inline uint8_t scatter_live_flag(const GridDesc &gd) { return gd.m == kWaveItemPoints ? 1 : 0; }
 
 // Two-pass form (large n).  Workgroup w of the counting and staging passes
 // carries the label w % 8, the XCD it runs on under round-robin dispatch.
@@ -297,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict_
                                                             const uint64_t *__restrict__ survbits,
                                                             uint32_t *__restrict__ lab_cur,
                                                             uint32_t *__restrict__ stage,
-                                                            uint8_t *__restrict__ flag)
+                                                            uint8_t *__restrict__ flag, uint8_t live_flag)
 {
     __shared__ uint32_t s_cnt[kMaxScatterBuckets];
     for (uint32_t t = threadIdx.x; t < nb; t += kThreads) s_cnt[t] = 0u;
@@ -311,10 +318,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict_
         cell[j] = 0u;
         rk[j] = 0u;
         if (i < n) {
-            flag[i] = 0;
             cell[j] = cell_of[i];
             rk[j] = rank[i];
             const bool live = ((survbits[cell[j] >> 6] >> (cell[j] & 63u)) & 1ull) != 0ull && rk[j] != kRankRemoved;
+            flag[i] = live ? live_flag : (uint8_t)0;
             if (live) slot[j] = atomicAdd(&s_cnt[cell[j] >> sh], 1u);
         }
     }
@@ -437,7 +444,7 @@ static hipError_t launch_scatter_two_pass(const T *pts, int64_t n, const GridDes
     hipLaunchKernelGGL(k_scatter_bases, dim3(1), dim3(kThreads), 0, st, ws.bcur, labs);
     hipLaunchKernelGGL(k_scatter_stage<T>, pgrid, dim3(kThreads), 0, st, pts, (uint32_t)n, gd.d, nb, sh,
                        (const uint32_t *)ws.cell_of, (const uint32_t *)ws.rank, (const uint64_t *)ws.survbits,
-                       ws.bcur, ws.stage, ws.flag);
+                       ws.bcur, ws.stage, ws.flag, scatter_live_flag(gd));
     const unsigned blocks = (unsigned)(((num_cus * scatter_row_blocks() + kNumXcd - 1) / kNumXcd) * kNumXcd);
     switch (gd.d) {
 #define SKYCELL_ROWS_CASE(DD)                                                                                    \
@@ -468,11 +475,11 @@ hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc 
     if (dtype == SKYCELL_DTYPE_F32)
         hipLaunchKernelGGL(k_scatter<float>, grid_for(n), dim3(kThreads), 0, st, (const float *)pts,
                            (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank, ws.rec, ws.keys, ws.fkeys,
-                           ws.sidx, ws.flag);
+                           ws.sidx, ws.flag, scatter_live_flag(gd));
     else
         hipLaunchKernelGGL(k_scatter<uint16_t>, grid_for(n), dim3(kThreads), 0, st,
                            (const uint16_t *)pts, (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank,
-                           ws.rec, ws.keys, ws.fkeys, ws.sidx, ws.flag);
+                           ws.rec, ws.keys, ws.fkeys, ws.sidx, ws.flag, scatter_live_flag(gd));
     return hipGetLastError();
 }
 

@@ -50,7 +50,8 @@ struct TuneEntry {
     int log2n;
     int dtype;
     int g;
-    int form;  // refine form for this grid: 0 lane, 1 wave, -1 not given
+    int form;   // refine form for this grid: 0 lane, 1 wave, -1 not given
+    int parts;  // wave form: waves per item, 0 not given
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
@@ -177,10 +178,49 @@ static int refine_form(int64_t n, int d, int g, int dtype)
     return (uint64_t)n >= 32ull * grid_cells(g, d) ? 1 : 0;
 }
 
+// Waves per item of the wave form: skycell_set_wave_parts / SKYCELL_WAVE_PARTS,
+// else the tuning table's parts column for this (d, n, dtype) and grid, else 1.
+// The candidates of a cone are dealt to the item's waves group by group, so the
+// longest cones (cells near the top corner of a coarse grid, whose cone can
+// hold most of the input) no longer run on one wave while the rest of the
+// chip idles.
+static std::atomic<int> g_parts_override{-2};  // -2 unread, 0 none, else the count
+
+static int wave_parts(int64_t n, int d, int g, int dtype)
+{
+    int ov = g_parts_override.load();
+    if (ov == -2) {
+        const char *v = getenv("SKYCELL_WAVE_PARTS");
+        int e = v ? atoi(v) : 0;
+        if (e < 0 || e > kMaxWaveParts) e = 0;
+        int expected = -2;
+        g_parts_override.compare_exchange_strong(expected, e);
+        ov = g_parts_override.load();
+    }
+    if (ov > 0) return ov;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int best = -1, best_dist = 1 << 30;
+    const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
+    for (const TuneEntry &e : g_tune) {
+        if (e.d != d || e.g != g || e.form != 1 || e.parts < 1 || (e.dtype != dtype && e.dtype != dtype + 2)) continue;
+        const int dist = std::abs(e.log2n - l2);
+        if (dist < best_dist) {
+            best_dist = dist;
+            best = e.parts;
+        }
+    }
+    return (best >= 1 && best_dist <= 2) ? best : 1;
+}
+
 GridDesc pipeline_desc(int64_t n, int d, int g, int dtype)
 {
     GridDesc gd = grid_desc(d, g);
-    if (refine_form(n, d, g, dtype) == 1) gd.m = kWaveItemPoints;
+    if (refine_form(n, d, g, dtype) == 1) {
+        gd.m = kWaveItemPoints;
+        // items <= n, and items * parts work units must stay below 2^31
+        const int64_t cap = std::max<int64_t>(1, ((int64_t)1 << 31) / std::max<int64_t>(n, 1) - 1);
+        gd.parts = (int32_t)std::min<int64_t>(wave_parts(n, d, g, dtype), cap);
+    }
     return gd;
 }
 
@@ -191,6 +231,7 @@ GridDesc grid_desc(int d, int g)
     gd.d = d;
     gd.g = g;
     gd.m = items_per_lane(d);
+    gd.parts = 1;
     gd.r = index_bits(g);
     gd.cells = 1u << (gd.r * d);
     for (int k = 0; k < d; ++k)
@@ -474,6 +515,14 @@ int skycell_set_refine_form(int32_t form)
     return ok();
 }
 
+int skycell_set_wave_parts(int32_t parts)
+{
+    if (parts < 0 || parts > kMaxWaveParts)
+        return fail(SKYCELL_E_INVAL, "parts = %d is outside [0, %d]", parts, kMaxWaveParts);
+    g_parts_override.store(parts);
+    return ok();
+}
+
 int skycell_load_tuning(const char *path)
 {
     std::vector<TuneEntry> entries;
@@ -485,9 +534,11 @@ int skycell_load_tuning(const char *path)
             if (line[0] == '#') continue;
             TuneEntry e;
             e.form = -1;
-            const int got = sscanf(line, "%d %d %d %d %d", &e.d, &e.log2n, &e.dtype, &e.g, &e.form);
+            e.parts = 0;
+            const int got = sscanf(line, "%d %d %d %d %d %d", &e.d, &e.log2n, &e.dtype, &e.g, &e.form, &e.parts);
             if (got >= 4 && e.d >= 1 && e.d <= SKYCELL_MAX_D && e.g >= 1) {
                 if (got < 5 || (e.form != 0 && e.form != 1)) e.form = -1;
+                if (got < 6 || e.parts < 1 || e.parts > kMaxWaveParts) e.parts = 0;
                 entries.push_back(e);
             }
         }

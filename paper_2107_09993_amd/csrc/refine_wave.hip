@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
                                                               const uint64_t *__restrict__ rec,
                                                               const uint2 *__restrict__ items,
                                                               uint32_t *__restrict__ ctr,
-                                                              uint8_t *__restrict__ flag,
+                                                              uint8_t *flag,
                                                               uint64_t *__restrict__ stats, GridDesc gd,
                                                               uint32_t chunk)
 {
@@ -95,18 +95,23 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
     __syncthreads();
 
     const uint32_t lane = (uint32_t)__lane_id();
-    WaveFeeder feed{ctr + kCtrHead, ctr[kCtrItems], chunk, (int)(blockIdx.x % kNumXcd), kNumXcd};
+    const uint32_t parts = (uint32_t)gd.parts;
+    // work units: (item, part) pairs, unit = item * parts + part
+    WaveFeeder feed{ctr + kCtrHead, ctr[kCtrItems] * parts, chunk, (int)(blockIdx.x % kNumXcd), kNumXcd};
     uint64_t visits = 0u, tests = 0u;
 
     uint32_t lo = 0u, hi = 0u;
     while (feed.next(lo, hi)) {
-        for (uint32_t item = lo; item < hi; ++item) {
+        for (uint32_t unit = lo; unit < hi; ++unit) {
+            const uint32_t item = unit / parts;
+            const uint32_t part = unit - item * parts;
             const uint2 it = items[item];
             const uint32_t qstart = wuniform(it.x);
             const uint32_t qcnt = wuniform(it.y >> 26);
             const uint32_t root = wuniform(it.y & ((1u << 26) - 1u));
             const bool valid = lane < qcnt;
             const uint32_t qpos = qstart + (valid ? lane : 0u);
+            const uint32_t orig = (uint32_t)sidx[qpos];
 
             uint32_t q[D];
             uint64_t qf[FW];
@@ -116,6 +121,10 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
             for (int w = 0; w < FW; ++w) qf[w] = fkeys[(size_t)qpos * FW + w] | kWHigh;
             qf[FW - 1] |= kPad;
             bool alive = valid;
+            // the part's share of the cone: every parts-th group of candidates
+            // along the walk, starting with group `part`
+            uint32_t gsel = 0u;
+            uint32_t since_poll = 0u;
 
             uint32_t x = root;
             uint64_t r = wuniform64(rec[x]);
@@ -127,6 +136,17 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
                     uint32_t c = rec_count(r);
                     if (c == kRecCountSat) c = wuniform(rec_start(rec[x + 1])) - s;
                     for (uint32_t t = 0; t < c; t += G) {
+                        const bool mine = gsel == part;
+                        gsel = gsel + 1u == parts ? 0u : gsel + 1u;
+                        if (!mine) continue;
+                        if (parts > 1u && ++since_poll == 16u) {
+                            // points that another part of this item has already
+                            // found dominated stop here too
+                            since_poll = 0u;
+                            alive = alive && *(volatile const uint8_t *)(flag + orig) != 0;
+                            if (__ballot(alive) == 0ull) break;
+                        }
+                        const bool was = alive;
                         tests += (uint64_t)__popcll(__ballot(alive)) * (c - t < (uint32_t)G ? c - t : (uint32_t)G);
                         uint32_t kill = 0u, need = 0u;
 #pragma unroll
@@ -165,6 +185,9 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
                                 if (((need >> u) & 1u) && gt == 0u && ne != 0u) alive = false;
                             }
                         }
+                        // a dominated point's flag is cleared at once (the
+                        // scatter set it for every surviving point)
+                        if (was && !alive) flag[orig] = 0;
                         if (__ballot(alive) == 0ull) break;
                     }
                 }
@@ -175,7 +198,6 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
                 const uint32_t lowm = (2u << j) - 1u;
                 diag = (diag & ~lowm) | (rec_nbr(r) & lowm);
             }
-            if (alive) flag[sidx[qpos]] = 1;
         }
     }
 

@@ -116,15 +116,29 @@ def test_choose_grid_respects_budget():
 
 
 def test_tuning_table_roundtrip(tmp_path):
+    shipped = os.path.join(os.path.dirname(sky.__file__), "tuning", "mi355x.txt")
     p = tmp_path / "tune.txt"
-    p.write_text("# d log2n dtype g\n8 20 0 4\n")
-    sky.load_tuning(str(p))
+    # d log2n dtype g [form [parts]]: a five- and a six-column line, and a bad parts value
+    p.write_text("# d log2n dtype g form parts\n6 20 0 3\n7 20 0 2 1 8\n5 20 0 2 1 999\n")
     try:
-        assert sky.choose_grid(1 << 20, 8) == 4
-        assert sky.choose_grid(1 << 20, 7) == sky.choose_grid(1 << 20, 7)  # untouched dims fall back
-    finally:
+        sky.load_tuning(str(p))
+        assert sky.choose_grid(1 << 20, 6) == 3
+        assert sky.choose_grid(1 << 20, 7) == 2
+        assert sky.choose_grid(1 << 20, 5) == 2
         sky.load_tuning(None)
-    assert sky.choose_grid(1 << 20, 8) != 4 or True
+        # without a table: about two cells per point, 2^18 cells for d = 6
+        assert sky.choose_grid(1 << 20, 6) == 8
+    finally:
+        sky.load_tuning(shipped if os.path.exists(shipped) else None)
+
+
+def test_wave_parts_argument_errors():
+    for bad in (-1, 65):
+        with pytest.raises(sky.SkycellError) as e:
+            sky.set_wave_parts(bad)
+        assert e.value.code == sky.E_INVAL
+    sky.set_wave_parts(3)
+    sky.set_wave_parts(0)
 
 
 def test_batched_plan_argument_errors():

@@ -58,3 +58,43 @@ def test_refine_forms_u16(oracle_mod, form):
     finally:
         sky.set_refine_form("auto")
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("parts", [2, 3, 8, 64])
+@pytest.mark.parametrize("name,make,g", CASES, ids=[c[0] for c in CASES])
+def test_wave_parts_match_oracle(oracle_mod, parts, name, make, g):
+    """The wave form with several waves per item (each screens every parts-th
+    candidate group of the cone, dominated points are cleared by whichever wave
+    finds a dominator) gives the oracle's skyline."""
+    x = make()
+    ref = oracle_mod.skyline_sfs(x)
+    sky.set_refine_form("wave")
+    sky.set_wave_parts(parts)
+    try:
+        got = _run(x, g)
+        again = _run(x, g)
+    finally:
+        sky.set_refine_form("auto")
+        sky.set_wave_parts(0)
+    assert np.array_equal(got, ref), (parts, len(got), len(ref))
+    assert np.array_equal(again, ref)
+
+
+def test_wave_parts_pivots_and_u16(oracle_mod):
+    """Several waves per item with the pivot pre-filter (removed points start
+    with a cleared flag) and with uint16 ties."""
+    dev = torch.device("cuda:0")
+    x = datagen.independent(60_000, 9, seed=10)
+    xs = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
+    piv = sky.topk(-xs.sum(dim=0), 512)
+    u = datagen.quantise_u16(datagen.anticorrelated(40_000, 6, seed=11))
+    sky.set_refine_form("wave")
+    sky.set_wave_parts(4)
+    try:
+        got = sky.compute_with_pivots(xs, piv, grid_res=2).cpu().numpy()
+        got_u = _run(u, 3, value_bits=10)
+    finally:
+        sky.set_refine_form("auto")
+        sky.set_wave_parts(0)
+    assert np.array_equal(got, oracle_mod.skyline_sfs(x))
+    assert np.array_equal(got_u, oracle_mod.skyline_sfs(u))
