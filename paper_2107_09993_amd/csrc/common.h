@@ -155,7 +155,8 @@ hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uin
                          int num_cus, hipStream_t st);
 hipError_t refine_prepare(const GridDesc &gd);
 // Wave form (refine_wave.hip), used when gd.m == kWaveItemPoints.
-hipError_t launch_refine_wave(const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus, hipStream_t st);
+hipError_t launch_refine_wave(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus,
+                              hipStream_t st);
 hipError_t refine_wave_prepare(const GridDesc &gd);
 hipError_t launch_output(int64_t n, const Workspace &ws, int32_t *out_idx, int32_t *out_count,
                          uint64_t *stats, hipStream_t st);

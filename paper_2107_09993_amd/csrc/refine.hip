@@ -113,11 +113,25 @@ static int refine_blocks_per_cu()
     return blocks_per_cu;
 }
 
+// Workgroups of a lane-form launch: enough to keep every CU at its resident
+// limit, but no more than the items can use.  There are at most n items (each
+// holds at least one point), and a wave takes `chunk` items per request, so
+// n / (chunk * waves per workgroup) workgroups already give every wave work;
+// small instances then leave the rest of the chip to concurrent kernels.
 template <int D, int M>
-static hipError_t launch_refine_dm(const GridDesc &gd, const Workspace &ws, uint64_t *stats,
+static unsigned refine_blocks(int64_t n, int num_cus)
+{
+    const uint64_t full = (uint64_t)num_cus * (uint64_t)refine_blocks_per_cu<D, M>();
+    const uint64_t per_block = (uint64_t)refine_chunk() * (kRefineThreads / kWave);
+    const uint64_t need = ((uint64_t)(n > 0 ? n : 1) + per_block - 1) / per_block;
+    return (unsigned)(need < full ? need : full);
+}
+
+template <int D, int M>
+static hipError_t launch_refine_dm(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                                    int num_cus, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)(num_cus * refine_blocks_per_cu<D, M>());
+    const unsigned blocks = refine_blocks<D, M>(n, num_cus);
     hipLaunchKernelGGL((k_refine<D, M>), dim3(blocks), dim3(kRefineThreads), 0, st,
                        (const uint32_t *)ws.keys, (const uint64_t *)ws.fkeys, (const int32_t *)ws.sidx,
                        (const uint64_t *)ws.rec, (const uint2 *)ws.items, ws.ctr, ws.flag, gd,
@@ -126,16 +140,16 @@ static hipError_t launch_refine_dm(const GridDesc &gd, const Workspace &ws, uint
 }
 
 template <int D>
-static hipError_t launch_refine_d(const GridDesc &gd, const Workspace &ws, uint64_t *stats,
+static hipError_t launch_refine_d(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                                   int num_cus, hipStream_t st)
 {
     switch (gd.m) {
     case 1:
-        return launch_refine_dm<D, 1>(gd, ws, stats, num_cus, st);
+        return launch_refine_dm<D, 1>(n, gd, ws, stats, num_cus, st);
     case 2:
-        return launch_refine_dm<D, 2>(gd, ws, stats, num_cus, st);
+        return launch_refine_dm<D, 2>(n, gd, ws, stats, num_cus, st);
     case 4:
-        return launch_refine_dm<D, 4>(gd, ws, stats, num_cus, st);
+        return launch_refine_dm<D, 4>(n, gd, ws, stats, num_cus, st);
     default:
         return hipErrorInvalidValue;
     }
@@ -194,12 +208,11 @@ hipError_t refine_prepare(const GridDesc &gd)
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st)
 {
-    (void)n;
-    if (gd.m == kWaveItemPoints) return launch_refine_wave(gd, ws, stats, num_cus, st);
+    if (gd.m == kWaveItemPoints) return launch_refine_wave(n, gd, ws, stats, num_cus, st);
     switch (gd.d) {
 #define SKYCELL_REFINE_CASE(DD) \
     case DD:                    \
-        return launch_refine_d<DD>(gd, ws, stats, num_cus, st);
+        return launch_refine_d<DD>(n, gd, ws, stats, num_cus, st);
         SKYCELL_REFINE_CASE(1)
         SKYCELL_REFINE_CASE(2)
         SKYCELL_REFINE_CASE(3)

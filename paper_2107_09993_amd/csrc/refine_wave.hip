@@ -232,11 +232,27 @@ static int wave_blocks_per_cu()
     return blocks_per_cu;
 }
 
+// Workgroups of a launch: the resident limit of the chip, or fewer when the
+// work units cannot use them.  A cell with m points gives ceil(m / 63) items,
+// so there are at most min(n, cells) + n / 63 items and `parts` units per item,
+// and a workgroup runs kWaveThreads / 64 units at a time.
 template <int D>
-static hipError_t launch_wave_d(const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus,
+static unsigned wave_blocks(int64_t n, const GridDesc &gd, int num_cus)
+{
+    const uint64_t full = (uint64_t)num_cus * (uint64_t)wave_blocks_per_cu<D>();
+    const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
+    const uint64_t items = (nn < gd.cells ? nn : (uint64_t)gd.cells) + (nn + kWaveItemPoints - 1) / kWaveItemPoints;
+    const uint64_t waves = items * (uint64_t)gd.parts;
+    const uint64_t per_block = kWaveThreads / 64;
+    const uint64_t need = (waves + per_block - 1) / per_block;
+    return (unsigned)(need < full ? need : full);
+}
+
+template <int D>
+static hipError_t launch_wave_d(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus,
                                 hipStream_t st)
 {
-    const unsigned blocks = (unsigned)(num_cus * wave_blocks_per_cu<D>());
+    const unsigned blocks = wave_blocks<D>(n, gd, num_cus);
     hipLaunchKernelGGL(k_refine_wave<D>, dim3(blocks), dim3(kWaveThreads), 0, st, (const uint32_t *)ws.keys,
                        (const uint64_t *)ws.fkeys, (const int32_t *)ws.sidx, (const uint64_t *)ws.rec,
                        (const uint2 *)ws.items, ws.ctr, ws.flag, stats, gd, wave_chunk());
@@ -261,12 +277,13 @@ hipError_t refine_wave_prepare(const GridDesc &gd)
     }
 }
 
-hipError_t launch_refine_wave(const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus, hipStream_t st)
+hipError_t launch_refine_wave(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus,
+                              hipStream_t st)
 {
     switch (gd.d) {
 #define SKYCELL_WAVE_LAUNCH(DD) \
     case DD:                    \
-        return launch_wave_d<DD>(gd, ws, stats, num_cus, st);
+        return launch_wave_d<DD>(n, gd, ws, stats, num_cus, st);
         SKYCELL_WAVE_EACH_D(SKYCELL_WAVE_LAUNCH)
 #undef SKYCELL_WAVE_LAUNCH
     default:
