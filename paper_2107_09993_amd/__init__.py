@@ -248,7 +248,7 @@ def compute(points, grid_res=0, layout="nd", value_bits=10, return_stats=False):
 
 
 class BatchedPlan:
-    """Many independent skylines in one persistent, graph-captured launch.
+    """Many independent skylines in one graph launch (captured at the first run).
 
     ns, ds: per-instance point counts and dimensionalities.  The points of all
     instances live in one device buffer of concatenated SoA blocks (see

@@ -12,6 +12,9 @@ item of the wave form):
     dtype 0 = binary32, single-instance calls (skycell_compute with grid_res 0)
     dtype 2 = binary32, instances of a batched plan
 
+dtype 2 rows come from a second sweep that times batched plans of 24
+instances of each shape (throughput under sharing, not one call's latency).
+
 Run on the GPU the table is meant for:
 
     python -m paper_2107_09993_amd.autotune --out paper_2107_09993_amd/tuning/mi355x.txt
@@ -50,8 +53,59 @@ def time_once(sky, torch, soa, n, d, g, reps):
     return best
 
 
+def time_batched(sky, torch, arrays, g, reps):
+    """Seconds per instance of one graph launch over `arrays` (all with grid g):
+    the instances of a batched plan share the chip, so what counts there is
+    throughput, not one instance's latency."""
+    dev = torch.device("cuda:0")
+    plan = sky.BatchedPlan([a.shape[0] for a in arrays], [a.shape[1] for a in arrays],
+                           grid_res=[g] * len(arrays), device=dev)
+    buf = plan.pack(arrays)
+    plan.run(buf)  # captures the graph
+    torch.cuda.synchronize()
+    best = math.inf
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        plan.run(buf)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    plan.close()
+    return best / len(arrays)
+
+
 FORMS = ("lane", "wave")
 WAVE_PARTS = (1, 2, 4, 8, 16)
+BATCH_SEEDS = 8  # instances per distribution in a batched timing
+
+
+def sweep_batched(dims, sizes, reps=2, log=print):
+    """Per (d, n): the configuration with the highest throughput when
+    3 * BATCH_SEEDS instances of that shape run as one batched plan."""
+    import torch
+    import paper_2107_09993_amd as sky
+    from paper_2107_09993_amd import datagen
+
+    table = []
+    for d in dims:
+        for n in sizes:
+            max_cells = min(1 << 24, max(1 << 16, 32 * n))
+            grids = candidate_grids(n, d, max_cells)
+            configs = [(g, "lane", 1) for g in grids] + [(g, "wave", p) for g in grids for p in WAVE_PARTS]
+            arrays = [datagen.generate(dist, n, d, seed=200 + 10 * k + j)
+                      for k, dist in enumerate(datagen.DISTRIBUTIONS) for j in range(BATCH_SEEDS)]
+            per = {}
+            for g, f, p in configs:
+                sky.set_refine_form(f)
+                sky.set_wave_parts(p)
+                per[(g, f, p)] = time_batched(sky, torch, arrays, g, reps)
+            sky.set_refine_form("auto")
+            sky.set_wave_parts(0)
+            best = min(configs, key=lambda c: per[c])
+            l2 = int(round(math.log2(n)))
+            table.append((d, l2, best[0], FORMS.index(best[1]), best[2]))
+            log(json.dumps({"batched": True, "d": d, "n": n, "best": "%d/%s/%d" % best,
+                            "ms_per_instance": {"%d/%s/%d" % c: round(1e3 * t, 4) for c, t in per.items()}}))
+    return table
 
 
 def sweep(dims, sizes, reps=2, log=print):
@@ -88,14 +142,18 @@ def sweep(dims, sizes, reps=2, log=print):
     return table
 
 
-def write_table(table, path):
+def write_table(table, path, batched=None):
+    """dtype 0 rows from the single-call sweep; dtype 2 rows from the batched
+    sweep when given, else the single-call choices."""
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
         f.write("# d log2n dtype g form parts  -- grid resolution, refine form (0 lane, 1 wave) and\n")
-        f.write("# waves per item of the wave form with the lowest mean time over the independent,\n")
-        f.write("# correlated and anti-correlated inputs (paper_2107_09993_amd.autotune)\n")
+        f.write("# waves per item of the wave form: dtype 0 with the lowest mean time of one call over\n")
+        f.write("# the independent, correlated and anti-correlated inputs, dtype 2 with the highest\n")
+        f.write("# throughput of batched plans of such instances (paper_2107_09993_amd.autotune)\n")
         for d, l2, g, form, parts in table:
             f.write("%d %d 0 %d %d %d\n" % (d, l2, g, form, parts))
+        for d, l2, g, form, parts in (batched if batched is not None else table):
             f.write("%d %d 2 %d %d %d\n" % (d, l2, g, form, parts))
 
 
@@ -105,11 +163,14 @@ def main():
     ap.add_argument("--dims", default="2,3,4,5,6,7,8,9,10,11,12")
     ap.add_argument("--sizes", default="1000,4000,16000,64000,200000")
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true", help="dtype 2 rows copy the single-call choices")
     a = ap.parse_args()
     dims = [int(v) for v in a.dims.split(",")]
     sizes = [int(v) for v in a.sizes.split(",")]
-    table = sweep(dims, sizes, a.reps, log=lambda s: print(s, flush=True))
-    write_table(table, a.out)
+    log = lambda s: print(s, flush=True)
+    table = sweep(dims, sizes, a.reps, log=log)
+    batched = None if a.no_batched else sweep_batched(dims, sizes, a.reps, log=log)
+    write_table(table, a.out, batched)
     print("wrote", a.out, flush=True)
 
 
