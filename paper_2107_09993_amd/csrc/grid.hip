@@ -229,7 +229,7 @@ static inline uint8_t scatter_live_flag(const GridDesc &gd) { return gd.m == kWa
 // Inside each bucket's range of sorted positions the staged rows are grouped
 // by label, so the runs that workgroups of one XCD append are adjacent and
 // their lines are completed in that XCD's L2.
-constexpr int kStagePts = 8;  // points per thread in the counting and staging passes
+constexpr int kStagePts = 16;  // points per thread in the counting and staging passes
 
 // Pass 1a: per-workgroup bucket counts of the points that survive (their cell
 // survives and the pivot pre-filter kept them), added into lab_cnt[bucket][label].
