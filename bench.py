@@ -175,7 +175,7 @@ def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the skyline on a single "
+        print("bench.py measures one GPU only: the library runs each skyline on a single "
               "MI355X and has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)"
               % (a.gpus, world), file=sys.stderr)
         sys.exit(2)

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``): only ``tests/``,
 ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg use it.
 
 The proposer is not part of the paper: it is a scoring network bolted onto the
-exact method, which stays the judge of every output.  What it computes is fixed
+exact method, which still decides every output.  What it computes is fixed
 here, in float64, step by step:
 
 * features of a point x with g columns per dimension (2d values):

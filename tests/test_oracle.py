@@ -2,7 +2,7 @@
 special cases with textbook answers and brute force on tiny inputs.
 
 None of these runs on the GPU; they establish that the oracle is right before it
-is used to judge the HIP path.
+is used to check the HIP path.
 """
 import itertools
 import json
