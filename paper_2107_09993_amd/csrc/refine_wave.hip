@@ -67,6 +67,23 @@ __device__ __forceinline__ void uniform_fine(const uint64_t *__restrict__ fkeys,
     for (int w = 0; w < FW; ++w) f[w] = wuniform64(fkeys[(size_t)i * FW + w]);
 }
 
+// The same words through a vector load (every lane reads the same address):
+// the group's four loads then stay in flight together in VGPRs, where scalar
+// loads were waited one by one for lack of free SGPRs.
+template <int FW>
+__device__ __forceinline__ void broadcast_fine(const uint64_t *__restrict__ fkeys, uint32_t i, uint64_t (&f)[FW])
+{
+    asm("" : "+v"(i));
+    if constexpr (FW == 2) {
+        const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(fkeys + (size_t)i * 2);
+        f[0] = a.x;
+        f[1] = a.y;
+    } else {
+#pragma unroll
+        for (int w = 0; w < FW; ++w) f[w] = fkeys[(size_t)i * FW + w];
+    }
+}
+
 // The read-only arrays are separate restrict arguments, so that the compiler
 // can serve wave-uniform reads of them from the scalar data cache.
 template <int D>
@@ -149,23 +166,29 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
                         const bool was = alive;
                         tests += (uint64_t)__popcll(__ballot(alive)) * (c - t < (uint32_t)G ? c - t : (uint32_t)G);
                         uint32_t kill = 0u, need = 0u;
+                        // the group's screening words, issued together: past the
+                        // cell's last candidate the index is clamped to it (an
+                        // in-range load whose result is not used)
+                        uint64_t f[G][FW];
+#pragma unroll
+                        for (int u = 0; u < G; ++u) {
+                            const uint32_t ci = t + (uint32_t)u < c ? s + t + (uint32_t)u : s + c - 1u;
+                            broadcast_fine<FW>(fkeys, ci, f[u]);
+                        }
 #pragma unroll
                         for (int u = 0; u < G; ++u) {
                             const uint32_t ci = s + t + (uint32_t)u;
-                            if (t + (uint32_t)u < c) {  // wave-uniform
-                                uint64_t f[FW];
-                                uniform_fine<FW>(fkeys, ci, f);
-                                uint64_t nle = 0ull, nlt = 0ull;
+                            uint64_t nle = 0ull, nlt = 0ull;
 #pragma unroll
-                                for (int w = 0; w < FW; ++w) {
-                                    const uint64_t diff = qf[w] - f[w];
-                                    nle |= ~diff & kWHigh;
-                                    nlt |= ~(diff - kWOnes) & kWHigh;
-                                }
-                                const bool other = ci != qpos;  // never a point against itself
-                                if (other && nlt == 0ull) kill = 1u;
-                                if (other && nle == 0ull && nlt != 0ull) need |= 1u << u;
+                            for (int w = 0; w < FW; ++w) {
+                                const uint64_t diff = qf[w] - f[u][w];
+                                nle |= ~diff & kWHigh;
+                                nlt |= ~(diff - kWOnes) & kWHigh;
                             }
+                            // in range (wave-uniform), and never a point against itself
+                            const bool use = t + (uint32_t)u < c && ci != qpos;
+                            if (use && nlt == 0ull) kill = 1u;
+                            if (use && nle == 0ull && nlt != 0ull) need |= 1u << u;
                         }
                         alive = alive && kill == 0u;
                         need = alive ? need : 0u;
