@@ -5,8 +5,8 @@
 // A work item is up to 63 sorted points of one cell, one per lane; all of them
 // share the cell's lower cone.  The wave walks that cone once, in lockstep
 // (the same odometer walk as the lane form, with wave-uniform state), and at
-// every non-empty surviving cell it streams the cell's points four at a time
-// through wave-uniform loads: each candidate is screened against all 63 query
+// every non-empty surviving cell it streams the cell's points 16 or 32 at a time
+// through broadcast loads: each candidate is screened against all 63 query
 // points at once, lanes whose query is dominated drop out, and the wave moves
 // to the next item as soon as every query point of its item is dominated.
 // Per candidate this costs a handful of vector instructions for 63 tests,
@@ -59,17 +59,10 @@ struct WaveFeeder {
 };
 
 
-// Screening words of candidate i (wave-uniform index), as wave-uniform values.
-template <int FW>
-__device__ __forceinline__ void uniform_fine(const uint64_t *__restrict__ fkeys, uint32_t i, uint64_t (&f)[FW])
-{
-#pragma unroll
-    for (int w = 0; w < FW; ++w) f[w] = wuniform64(fkeys[(size_t)i * FW + w]);
-}
-
-// The same words through a vector load (every lane reads the same address):
-// the group's four loads then stay in flight together in VGPRs, where scalar
-// loads were waited one by one for lack of free SGPRs.
+// Screening words of candidate i (wave-uniform index) through a vector load
+// that every lane issues for the same address: a group's loads then stay in
+// flight together in VGPRs, where scalar loads were waited one by one for lack
+// of free SGPRs.
 template <int FW>
 __device__ __forceinline__ void broadcast_fine(const uint64_t *__restrict__ fkeys, uint32_t i, uint64_t (&f)[FW])
 {
@@ -100,7 +93,9 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
     constexpr int FW = fine_words(D);
     constexpr uint32_t kAll = (1u << D) - 1u;
     constexpr uint64_t kPad = (D % 8 == 0) ? 0ull : (~0ull << (8 * (D % 8))) & 0x7F7F7F7F7F7F7F7Full;
-    constexpr int G = 4;  // candidates per group
+    // candidates per group: more loads in flight, within the VGPRs a group
+    // of screening words takes (two words per candidate above d = 8)
+    constexpr int G = FW == 1 ? 32 : 16;
 
     __shared__ uint32_t s_mask[kMaxD], s_low[kMaxD];
     if (threadIdx.x < kMaxD) {
