@@ -7,7 +7,9 @@
 //       refine's cone walk;
 //   K2  exclusive scan of surviving-cell counts: counting-sort offsets and refine
 //       work items;
-//   K4  scatter of surviving points, grouped by cell, as order-preserving keys.
+//   K4  scatter of surviving points, grouped by cell, as order-preserving keys
+//       (one pass below 2^20 points; above, staged by ranges of cells first so
+//       that the final writes complete whole cache lines).
 #include <cstdlib>
 
 #include "cellops.h"
