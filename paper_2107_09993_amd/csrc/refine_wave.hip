@@ -93,9 +93,10 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
     constexpr int FW = fine_words(D);
     constexpr uint32_t kAll = (1u << D) - 1u;
     constexpr uint64_t kPad = (D % 8 == 0) ? 0ull : (~0ull << (8 * (D % 8))) & 0x7F7F7F7F7F7F7F7Full;
-    // candidates per group: more loads in flight, within the VGPRs a group
-    // of screening words takes (two words per candidate above d = 8)
-    constexpr int G = FW == 1 ? 32 : 16;
+    // candidates per group; up to d = 8 (one screening word per candidate)
+    // the next group's words are loaded while a group is screened, above it
+    // (two words) the registers of a second buffer cost more than they hide
+    constexpr int G = 16;
 
     __shared__ uint32_t s_mask[kMaxD], s_low[kMaxD];
     if (threadIdx.x < kMaxD) {
@@ -147,36 +148,40 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
                     const uint32_t s = rec_start(r);
                     uint32_t c = rec_count(r);
                     if (c == kRecCountSat) c = wuniform(rec_start(rec[x + 1])) - s;
-                    for (uint32_t t = 0; t < c; t += G) {
-                        const bool mine = gsel == part;
-                        gsel = gsel + 1u == parts ? 0u : gsel + 1u;
-                        if (!mine) continue;
+                    // this part's groups of the cell are i, i + parts, ...; the
+                    // next one's words are loaded while the current one is screened
+                    const uint32_t ng = (c + (uint32_t)G - 1u) / (uint32_t)G;
+                    uint32_t i = part >= gsel ? part - gsel : part + parts - gsel;
+                    gsel = (uint32_t)((gsel + ng) % parts);
+                    uint64_t fa[G][FW], fb[FW == 1 ? G : 1][FW];
+                    auto load_group = [&](uint64_t (&fv)[G][FW], uint32_t gi) {
+                        const uint32_t t = gi * (uint32_t)G;
+#pragma unroll
+                        for (int u = 0; u < G; ++u) {
+                            const uint32_t ci = t + (uint32_t)u < c ? s + t + (uint32_t)u : s + c - 1u;
+                            broadcast_fine<FW>(fkeys, ci, fv[u]);
+                        }
+                    };
+                    // screens group gi; false when every point of the item is dominated
+                    auto screen_group = [&](const uint64_t (&fv)[G][FW], uint32_t gi) -> bool {
+                        const uint32_t t = gi * (uint32_t)G;
                         if (parts > 1u && ++since_poll == 16u) {
                             // points that another part of this item has already
                             // found dominated stop here too
                             since_poll = 0u;
                             alive = alive && *(volatile const uint8_t *)(flag + orig) != 0;
-                            if (__ballot(alive) == 0ull) break;
+                            if (__ballot(alive) == 0ull) return false;
                         }
                         const bool was = alive;
                         tests += (uint64_t)__popcll(__ballot(alive)) * (c - t < (uint32_t)G ? c - t : (uint32_t)G);
                         uint32_t kill = 0u, need = 0u;
-                        // the group's screening words, issued together: past the
-                        // cell's last candidate the index is clamped to it (an
-                        // in-range load whose result is not used)
-                        uint64_t f[G][FW];
-#pragma unroll
-                        for (int u = 0; u < G; ++u) {
-                            const uint32_t ci = t + (uint32_t)u < c ? s + t + (uint32_t)u : s + c - 1u;
-                            broadcast_fine<FW>(fkeys, ci, f[u]);
-                        }
 #pragma unroll
                         for (int u = 0; u < G; ++u) {
                             const uint32_t ci = s + t + (uint32_t)u;
                             uint64_t nle = 0ull, nlt = 0ull;
 #pragma unroll
                             for (int w = 0; w < FW; ++w) {
-                                const uint64_t diff = qf[w] - f[u][w];
+                                const uint64_t diff = qf[w] - fv[u][w];
                                 nle |= ~diff & kWHigh;
                                 nlt |= ~(diff - kWOnes) & kWHigh;
                             }
@@ -206,7 +211,27 @@ __global__ __launch_bounds__(kWaveThreads) void k_refine_wave(const uint32_t *__
                         // a dominated point's flag is cleared at once (the
                         // scatter set it for every surviving point)
                         if (was && !alive) flag[orig] = 0;
-                        if (__ballot(alive) == 0ull) break;
+                        return __ballot(alive) != 0ull;
+                    };
+                    if constexpr (FW == 1) {
+                        if (i < ng) {
+                            load_group(fa, i);
+                            for (;;) {
+                                const uint32_t i1 = i + parts;
+                                if (i1 < ng) load_group(fb, i1);
+                                if (!screen_group(fa, i) || i1 >= ng) break;
+                                const uint32_t i2 = i1 + parts;
+                                if (i2 < ng) load_group(fa, i2);
+                                if (!screen_group(fb, i1) || i2 >= ng) break;
+                                i = i2;
+                            }
+                        }
+                    } else {
+                        (void)fb;
+                        for (; i < ng; i += parts) {
+                            load_group(fa, i);
+                            if (!screen_group(fa, i)) break;
+                        }
                     }
                 }
                 if (diag == 0u || __ballot(alive) == 0ull) break;
