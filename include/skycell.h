@@ -123,6 +123,26 @@ int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d,
                        uint64_t *stats, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): skycell_compute_ws
+ * without a workspace argument.  Its scratch is a fixed array of
+ * SKYCELL_STATIC_SCRATCH_BYTES inside the library, one per GPU, which that GPU
+ * holds from the library's first use on it until the process ends; nothing is
+ * allocated by this call.  Arguments and results are those of
+ * skycell_compute_ws (stats may be NULL).
+ *   Size limit: a call whose workspace (skycell_workspace_bytes for the same
+ *   n, d, grid_res and dtype) exceeds SKYCELL_STATIC_SCRATCH_BYTES returns
+ *   SKYCELL_E_NOMEM before touching the device.
+ *   Concurrency: every call on one GPU shares that GPU's array (each call
+ *   clears what it needs before use); calls that overlap in time on one GPU,
+ *   from any stream or thread, race on it and give undefined results.
+ */
+#define SKYCELL_STATIC_SCRATCH_BYTES (64u << 20)
+int skycell_compute_static(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
+                           int32_t value_bits, int32_t *out_idx, int32_t *out_count, uint64_t *stats,
+                           void *stream);
+
+/*
  * Grid resolution the library uses when grid_res = 0: the autotuner's entry for
  * d and dtype whose log2 n is nearest to that of n (and at most 1 away) if a
  * tuning table is loaded, else a rule that keeps about one to two cells per

@@ -29,6 +29,7 @@ DTYPE_U16 = 1
 NUM_STATS = 9
 STAT_NAMES = ("nonempty_cells", "surviving_cells", "survivor_points", "items", "cell_visits",
               "pair_tests", "skyline", "grid_res", "pivot_removed")
+STATIC_SCRATCH_BYTES = 64 << 20
 MLP_HIDDEN = 64
 MAX_PIVOTS = 4096
 
@@ -54,6 +55,7 @@ def lib():
     L.skycell_compute_u16.argtypes = [p, i64, i32, i32, i32, p, p, p]
     L.skycell_workspace_bytes.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz)]
     L.skycell_compute_ws.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, sz, p, p]
+    L.skycell_compute_static.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, p]
     L.skycell_choose_grid.argtypes = [i64, i32, i32, ctypes.POINTER(i32)]
     L.skycell_load_tuning.argtypes = [ctypes.c_char_p]
     L.skycell_set_refine_form.argtypes = [i32]
@@ -85,7 +87,7 @@ def lib():
     L.skycell_last_error.argtypes = []
     L.skycell_last_error.restype = ctypes.c_char_p
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
-                 "skycell_compute_ws", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
+                 "skycell_compute_ws", "skycell_compute_static", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
                  "skycell_set_wave_parts",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
                  "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
@@ -245,6 +247,27 @@ def compute(points, grid_res=0, layout="nd", value_bits=10, return_stats=False):
     if return_stats:
         return out, sk.stats_dict()
     return out
+
+
+def compute_static(points_soa, grid_res=0, value_bits=10, out_idx=None, out_count=None, stats=None,
+                   stream=None):
+    """Skyline of a contiguous [d, n] tensor with the library's fixed scratch
+    array (skycell_compute_static: no device allocation inside the library).
+    out_idx (int32 [n]) and out_count (int32 [1]) may be passed in so that the
+    call allocates nothing at all; returns (out_idx, out_count) unsynchronised."""
+    import torch
+    if not points_soa.is_contiguous() or points_soa.dim() != 2:
+        raise ValueError("points must be a contiguous [d, n] tensor")
+    d, n = points_soa.shape
+    dev = points_soa.device
+    if out_idx is None:
+        out_idx = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if out_count is None:
+        out_count = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().skycell_compute_static(_ptr(points_soa), _dtype_code(points_soa), n, d, int(grid_res),
+                                        int(value_bits), _ptr(out_idx), _ptr(out_count), _ptr(stats),
+                                        _stream(dev, stream)))
+    return out_idx, out_count
 
 
 class BatchedPlan:

@@ -216,3 +216,21 @@ def test_pivoted_argument_errors():
     assert lib.skycell_skyline_labels(None, FAKE, 5, FAKE, None) == sky.E_INVAL
     assert lib.skycell_mlp_score(None, FAKE, 10, 10, FAKE, None) == sky.E_INVAL
     assert lib.skycell_mlp_train_step(None, FAKE, 10, FAKE, 10, ctypes.c_float(0.1), None, None) == sky.E_INVAL
+
+
+def test_static_entry_point_rejects_sizes_over_its_scratch():
+    """skycell_compute_static refuses, on the host, any call whose workspace
+    exceeds the fixed scratch array, and validates its arguments first."""
+    lib = sky.lib()
+    src = open(HEADER).read()
+    assert re.search(r"SKYCELL_STATIC_SCRATCH_BYTES \(64u << 20\)", src)
+    assert sky.STATIC_SCRATCH_BYTES == 64 << 20
+    n = 2_000_000
+    assert sky.workspace_bytes(n, 8, 8) > sky.STATIC_SCRATCH_BYTES
+    rc = lib.skycell_compute_static(FAKE, sky.DTYPE_F32, n, 8, 8, 0, FAKE, FAKE, None, None)
+    assert rc == sky.E_NOMEM
+    assert "static scratch" in sky.last_error()
+    rc = lib.skycell_compute_static(None, sky.DTYPE_F32, 100, 4, 8, 0, FAKE, FAKE, None, None)
+    assert rc == sky.E_INVAL
+    rc = lib.skycell_compute_static(FAKE, sky.DTYPE_U16, 100, 4, 8, 17, FAKE, FAKE, None, None)
+    assert rc == sky.E_RANGE
