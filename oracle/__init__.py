@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path
 (``paper_2107_09993_amd``) never does, and the two share no code.
 
-* ``skyline_bruteforce`` (O1) and ``skyline_sfs`` (O2) come from the C file
-  ``skyline_oracle.c`` compiled with gcc by :func:`build`.
+* ``skyline_bruteforce`` (O1), ``skyline_sfs`` (O2) and ``skyline_kdtree`` (O3,
+  an orthant-emptiness test on a k-d tree, for inputs of 10^6 points and more)
+  come from the C file ``skyline_oracle.c`` compiled with gcc by :func:`build`.
 * ``skyline_pure_python`` is a third, tiny implementation of the definition for
   exhaustive checks on very small inputs.
 * ``cells`` holds the cell-level definitions (Definitions 3-6, Equations 5-14).
@@ -48,8 +49,8 @@ def _load():
     build()
     lib = ctypes.CDLL(_LIB_PATH)
     i64, i32, p = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
-    for name in ("orc_skyline_brute_f32", "orc_skyline_sfs_f32",
-                 "orc_skyline_brute_u16", "orc_skyline_sfs_u16"):
+    for name in ("orc_skyline_brute_f32", "orc_skyline_sfs_f32", "orc_skyline_kdtree_f32",
+                 "orc_skyline_brute_u16", "orc_skyline_sfs_u16", "orc_skyline_kdtree_u16"):
         f = getattr(lib, name)
         f.argtypes = [p, i64, i32, p, i32]
         f.restype = i64
@@ -106,6 +107,12 @@ def skyline_bruteforce(points, nthreads=None):
 def skyline_sfs(points, nthreads=None):
     """O2: sort-first skyline with an exact linear-extension key."""
     return _run("sfs", points, nthreads)
+
+
+def skyline_kdtree(points, nthreads=None):
+    """O3: for each point, is the closed lower orthant {q <= p} free of points
+    other than copies of p?  Answered on a k-d tree with bounding boxes."""
+    return _run("kdtree", points, nthreads)
 
 
 def is_skyline(points, indices, nthreads=None):

@@ -272,8 +272,19 @@ static int64_t sfs_core(const double *w, int64_t n, int d, int32_t *out, int nth
         return ORC_E_NOMEM;
     }
     for (int64_t i = 0; i < n; ++i) {
+        /* Infinities are clamped to +-2^129 (beyond every finite binary32)
+         * before summing, so that a point holding both +inf and -inf gets a
+         * finite sum instead of NaN.  The clamp is non-decreasing, so the sum
+         * stays a monotone function of the coordinates and the key remains a
+         * linear extension of the dominance order; ties still fall back to
+         * the unclamped coordinates. */
         double s = 0.0;
-        for (int k = 0; k < d; ++k) s += w[(size_t)i * d + k];
+        for (int k = 0; k < d; ++k) {
+            double v = w[(size_t)i * d + k];
+            if (v > 0x1p129) v = 0x1p129;
+            if (v < -0x1p129) v = -0x1p129;
+            s += v;
+        }
         sum[i] = s;
         order[i] = i;
     }
@@ -409,6 +420,214 @@ int orc_is_skyline_u16(const uint16_t *pts, int64_t n, int d, const int64_t *idx
     parallel_for(nthreads, m, 1, check_range, &c);
     free(w);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* O3: orthant-emptiness test on a k-d tree.                           */
+/*                                                                    */
+/* By Definitions 1-2, p is a skyline point iff no point q satisfies   */
+/* q <= p in every dimension with q != p as a vector (q <= p and       */
+/* q != p is exactly "q dominates p").  So the oracle asks, for each   */
+/* p, whether the closed lower orthant {q : q <= p} holds a point that */
+/* differs from p.  A k-d tree over all points answers this with       */
+/* bounding boxes of the actual points in each node:                  */
+/*   - a node whose box minimum exceeds p in some dimension holds no   */
+/*     point of the orthant and is skipped;                           */
+/*   - a node whose box maximum is <= p everywhere lies inside the     */
+/*     orthant; it holds a point != p iff its box minimum is below p   */
+/*     in some dimension (otherwise min = max = p: only copies of p);  */
+/*   - a leaf is scanned point by point with Definition 1.             */
+/* The search stops at the first dominator.  Only comparisons are used */
+/* (binary64 widened inputs), so the result is exact.                  */
+/* ------------------------------------------------------------------ */
+#define KD_LEAF 24
+
+typedef struct {
+    int64_t lo, hi;       /* points tp[lo .. hi) in tree order */
+    int32_t left, right;  /* child nodes, -1 for a leaf */
+} kd_node;
+
+typedef struct {
+    int d;
+    const double *w;      /* original points, row-major */
+    double *tp;           /* points copied in tree order */
+    int64_t *perm;        /* tree position -> original index */
+    kd_node *nodes;
+    double *bmin, *bmax;  /* per node, d values each */
+    int64_t nnodes, cap;
+} kd_tree;
+
+static double kd_val(const kd_tree *t, int64_t pos, int k) { return t->w[(size_t)t->perm[pos] * t->d + k]; }
+
+static void kd_swap(int64_t *a, int64_t i, int64_t j) { int64_t x = a[i]; a[i] = a[j]; a[j] = x; }
+
+/* Rearrange perm[lo..hi) so that position m holds the element of rank m - lo
+ * in dimension k, smaller-or-equal values before it and larger-or-equal after
+ * (quickselect with a three-way partition, so heavy ties stay linear). */
+static void kd_select(kd_tree *t, int64_t lo, int64_t hi, int64_t m, int k)
+{
+    int64_t *a = t->perm;
+    while (hi - lo > 1) {
+        const double x0 = kd_val(t, lo, k), x1 = kd_val(t, lo + (hi - lo) / 2, k), x2 = kd_val(t, hi - 1, k);
+        double pv = x0 < x1 ? (x1 < x2 ? x1 : (x0 < x2 ? x2 : x0)) : (x0 < x2 ? x0 : (x1 < x2 ? x2 : x1));
+        int64_t lt = lo, i = lo, gt = hi;  /* [lo,lt) < pv, [lt,i) == pv, [gt,hi) > pv */
+        while (i < gt) {
+            const double v = kd_val(t, i, k);
+            if (v < pv) kd_swap(a, lt++, i++);
+            else if (v > pv) kd_swap(a, i, --gt);
+            else ++i;
+        }
+        if (m < lt) hi = lt;
+        else if (m >= gt) lo = gt;
+        else return;
+    }
+}
+
+static int32_t kd_new_node(kd_tree *t, int64_t lo, int64_t hi)
+{
+    if (t->nnodes == t->cap) return -1;
+    const int32_t id = (int32_t)t->nnodes++;
+    t->nodes[id].lo = lo;
+    t->nodes[id].hi = hi;
+    t->nodes[id].left = t->nodes[id].right = -1;
+    double *mn = t->bmin + (size_t)id * t->d, *mx = t->bmax + (size_t)id * t->d;
+    for (int k = 0; k < t->d; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
+    for (int64_t i = lo; i < hi; ++i)
+        for (int k = 0; k < t->d; ++k) {
+            const double v = kd_val(t, i, k);
+            if (v < mn[k]) mn[k] = v;
+            if (v > mx[k]) mx[k] = v;
+        }
+    return id;
+}
+
+/* Split on the dimension of widest extent, at the median. */
+static int kd_build(kd_tree *t, int32_t id)
+{
+    const int64_t lo = t->nodes[id].lo, hi = t->nodes[id].hi;
+    if (hi - lo <= KD_LEAF) return ORC_OK;
+    const double *mn = t->bmin + (size_t)id * t->d, *mx = t->bmax + (size_t)id * t->d;
+    int k = 0;
+    double best = 0.0;
+    for (int j = 0; j < t->d; ++j) {
+        const double ext = mx[j] > mn[j] ? mx[j] - mn[j] : 0.0;  /* +inf for infinite ranges */
+        if (ext > best) { best = ext; k = j; }
+    }
+    if (best == 0.0) return ORC_OK;  /* all points of the node are copies: keep a leaf */
+    const int64_t mid = lo + (hi - lo) / 2;
+    kd_select(t, lo, hi, mid, k);
+    const int32_t l = kd_new_node(t, lo, mid), r = kd_new_node(t, mid, hi);
+    if (l < 0 || r < 0) return ORC_E_NOMEM;
+    t->nodes[id].left = l;
+    t->nodes[id].right = r;
+    int rc = kd_build(t, l);
+    if (rc == ORC_OK) rc = kd_build(t, r);
+    return rc;
+}
+
+typedef struct {
+    const kd_tree *t;
+    uint8_t *flag;   /* by original index: 1 = skyline */
+} kd_query_ctx;
+
+static int kd_has_dominator(const kd_tree *t, const double *p)
+{
+    const int d = t->d;
+    int32_t stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const int32_t id = stack[--sp];
+        const double *mn = t->bmin + (size_t)id * d, *mx = t->bmax + (size_t)id * d;
+        int outside = 0, inside = 1, below = 0;
+        for (int k = 0; k < d; ++k) {
+            if (mn[k] > p[k]) { outside = 1; break; }
+            if (mx[k] > p[k]) inside = 0;
+            if (mn[k] < p[k]) below = 1;
+        }
+        if (outside) continue;
+        if (inside) {
+            if (below) return 1;  /* some point of the node is <= p and != p */
+            continue;             /* the node holds only copies of p */
+        }
+        const kd_node *nd = &t->nodes[id];
+        if (nd->left < 0) {
+            for (int64_t i = nd->lo; i < nd->hi; ++i)
+                if (dominates(t->tp + (size_t)i * d, p, d)) return 1;
+            continue;
+        }
+        /* the left child holds the smaller values of the split dimension:
+         * search it first, where dominators are more likely */
+        if (sp + 2 > 256) return -1;
+        stack[sp++] = nd->right;
+        stack[sp++] = nd->left;
+    }
+    return 0;
+}
+
+static int g_kd_overflow = 0;
+
+static void kd_query_range(void *vctx, int64_t lo, int64_t hi)
+{
+    kd_query_ctx *c = (kd_query_ctx *)vctx;
+    const kd_tree *t = c->t;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int r = kd_has_dominator(t, t->w + (size_t)i * t->d);
+        if (r < 0) __atomic_store_n(&g_kd_overflow, 1, __ATOMIC_RELAXED);
+        c->flag[i] = r == 0;
+    }
+}
+
+static int64_t kdtree_core(const double *w, int64_t n, int d, int32_t *out, int nthreads)
+{
+    if (n == 0) return 0;
+    kd_tree t;
+    memset(&t, 0, sizeof(t));
+    t.d = d;
+    t.w = w;
+    t.cap = n / 4 + 16;  /* median splits of nodes above KD_LEAF: fewer than n/6 + 2 nodes */
+    t.perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    t.tp = (double *)malloc(sizeof(double) * (size_t)n * (size_t)d);
+    t.nodes = (kd_node *)malloc(sizeof(kd_node) * (size_t)t.cap);
+    t.bmin = (double *)malloc(sizeof(double) * (size_t)t.cap * (size_t)d);
+    t.bmax = (double *)malloc(sizeof(double) * (size_t)t.cap * (size_t)d);
+    uint8_t *flag = (uint8_t *)malloc((size_t)n);
+    int64_t m = ORC_E_NOMEM;
+    if (!t.perm || !t.tp || !t.nodes || !t.bmin || !t.bmax || !flag) goto done;
+    for (int64_t i = 0; i < n; ++i) t.perm[i] = i;
+    if (kd_new_node(&t, 0, n) != 0 || kd_build(&t, 0) != ORC_OK) goto done;
+    for (int64_t i = 0; i < n; ++i)
+        memcpy(t.tp + (size_t)i * d, w + (size_t)t.perm[i] * d, sizeof(double) * (size_t)d);
+    g_kd_overflow = 0;
+    kd_query_ctx c = {&t, flag};
+    parallel_for(nthreads, n, 256, kd_query_range, &c);
+    if (g_kd_overflow) { m = ORC_E_INVAL; goto done; }
+    m = flags_to_indices(flag, n, out);
+done:
+    free(t.perm); free(t.tp); free(t.nodes); free(t.bmin); free(t.bmax); free(flag);
+    return m;
+}
+
+int64_t orc_skyline_kdtree_f32(const float *pts, int64_t n, int d, int32_t *out, int nthreads)
+{
+    if (!args_ok(pts, n, d, out)) return ORC_E_INVAL;
+    int nan = 0;
+    double *w = widen_f32(pts, n, d, &nan);
+    if (!w) return ORC_E_NOMEM;
+    if (nan) { free(w); return ORC_E_NAN; }
+    int64_t m = kdtree_core(w, n, d, out, nthreads);
+    free(w);
+    return m;
+}
+
+int64_t orc_skyline_kdtree_u16(const uint16_t *pts, int64_t n, int d, int32_t *out, int nthreads)
+{
+    if (!args_ok(pts, n, d, out)) return ORC_E_INVAL;
+    double *w = widen_u16(pts, n, d);
+    if (!w) return ORC_E_NOMEM;
+    int64_t m = kdtree_core(w, n, d, out, nthreads);
+    free(w);
+    return m;
 }
 
 /* ------------------------------------------------------------------ */

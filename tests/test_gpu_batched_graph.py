@@ -84,30 +84,6 @@ def test_graph_batched_nan_instance(oracle_mod):
     plan.close()
 
 
-def test_graph_batched_workload_shapes_sampled(oracle_mod):
-    """The first 256 instances of the batched workload (n log-uniform in
-    [1,000, 200,000], d uniform in 3..12, mixed distributions); every instance is
-    checked against the oracle, exhaustively where the sort-first oracle is
-    cheap and by sampled points elsewhere."""
-    dev = _dev()
-    shapes = datagen.batched_instances(count=4096)[:256]
-    arrays = [datagen.generate(dist, n, d, seed) for n, d, dist, seed in shapes]
-    plan = sky.BatchedPlan([a.shape[0] for a in arrays], [a.shape[1] for a in arrays], device=dev)
-    plan.run(plan.pack(arrays))
-    got = plan.results()
-    rng = np.random.default_rng(0)
-    for b, (a, g) in enumerate(zip(arrays, got)):
-        n, d = a.shape
-        if n <= 20_000 or shapes[b][2] == "correlated":
-            assert np.array_equal(g, oracle_mod.skyline_sfs(a)), "instance %d" % b
-        else:
-            flag = np.zeros(n, dtype=bool)
-            flag[g] = True
-            idx = rng.integers(0, n, size=40)
-            assert np.array_equal(oracle_mod.is_skyline(a, idx), flag[idx]), "instance %d" % b
-    plan.close()
-
-
 def test_graph_batched_merge_law(oracle_mod):
     """sky(A1 u ... u A8) = sky(sky(A1) u ... u sky(A8)): the parts' skylines from
     one batched launch, merged and reduced by the single-instance path, give the

@@ -298,6 +298,7 @@ def test_exhaustive_tiny(oracle_mod):
                 ref = oracle_mod.skyline_pure_python(pts)
                 assert np.array_equal(oracle_mod.skyline_bruteforce(pts), ref)
                 assert np.array_equal(oracle_mod.skyline_sfs(pts), ref)
+                assert np.array_equal(oracle_mod.skyline_kdtree(pts), ref)
                 if d == 2:
                     assert np.array_equal(_staircase_2d(pts), ref)
 
@@ -312,6 +313,8 @@ def test_random_ties_three_ways(oracle_mod, seed):
         u = pts.astype(np.uint16)
         assert np.array_equal(oracle_mod.skyline_sfs(u), ref)
         assert np.array_equal(oracle_mod.skyline_bruteforce(u), ref)
+        assert np.array_equal(oracle_mod.skyline_kdtree(pts), ref)
+        assert np.array_equal(oracle_mod.skyline_kdtree(u), ref)
 
 
 def test_sfs_matches_bruteforce_medium(oracle_mod):
@@ -350,3 +353,70 @@ def test_expected_skyline_size_plausibility(oracle_mod):
     assert 160 < e < 170
     sizes = [oracle_mod.skyline_sfs(datagen.independent(10_000, 4, seed=s)).size for s in range(8)]
     assert abs(np.mean(sizes) - e) < 0.15 * e
+
+
+# ---------------------------------------------------------------- O3 (k-d tree orthant test)
+@pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 12, 16])
+def test_kdtree_matches_bruteforce(oracle_mod, dist, d):
+    """O3 against the definition written out (O1) on inputs large enough for a
+    deep tree (leaves of 24 points), and against the sort-first skyline (O2)."""
+    pts = datagen.generate(dist, 6000 + 7 * d, d, seed=50 + d)
+    ref = oracle_mod.skyline_bruteforce(pts)
+    assert np.array_equal(oracle_mod.skyline_kdtree(pts), ref)
+    assert np.array_equal(oracle_mod.skyline_sfs(pts), ref)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kdtree_heavy_ties_duplicates_and_u16(oracle_mod, seed):
+    """Equal coordinates, exact copies (many in one leaf, whole subtrees of one
+    value) and integer data: copies never dominate each other."""
+    rng = np.random.default_rng(seed)
+    for d, high in ((2, 3), (4, 2), (5, 6), (7, 3)):
+        base = rng.integers(0, high, size=(3000, d))
+        pts = np.concatenate([base, base[:500], np.zeros((300, d), np.int64) + 1]).astype(np.float32)
+        ref = oracle_mod.skyline_bruteforce(pts)
+        assert np.array_equal(oracle_mod.skyline_kdtree(pts), ref)
+        assert np.array_equal(oracle_mod.skyline_kdtree(pts.astype(np.uint16)), ref)
+    same = np.ones((5000, 3), np.float32)
+    assert np.array_equal(oracle_mod.skyline_kdtree(same), np.arange(5000, dtype=np.int32))
+    u = datagen.quantise_u16(datagen.anticorrelated(20000, 6, seed=seed))
+    assert np.array_equal(oracle_mod.skyline_kdtree(u), oracle_mod.skyline_bruteforce(u))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_special_values_three_oracles(oracle_mod, seed):
+    """Infinities of both signs (a point may hold +inf and -inf together),
+    signed zeros and subnormals: O2 and O3 equal brute force."""
+    rng = np.random.default_rng(seed)
+    for n, d in ((400, 3), (3000, 5)):
+        pts = rng.random((n, d)).astype(np.float32)
+        specials = np.asarray([np.inf, -np.inf, 0.0, -0.0, 1e-45, -1e-45, 3e38, -3e38], np.float32)
+        mask = rng.random((n, d)) < 0.3
+        pts[mask] = specials[rng.integers(0, len(specials), size=mask.sum())]
+        ref = oracle_mod.skyline_bruteforce(pts)
+        assert np.array_equal(oracle_mod.skyline_sfs(pts), ref)
+        assert np.array_equal(oracle_mod.skyline_kdtree(pts), ref)
+
+
+def test_kdtree_matches_sfs_at_2e5(oracle_mod):
+    """Larger inputs: O3 against O2 on the three distributions at d = 8, and on
+    quantised data with ties."""
+    for dist in datagen.DISTRIBUTIONS:
+        pts = datagen.generate(dist, 200_000, 8, seed=9)
+        assert np.array_equal(oracle_mod.skyline_kdtree(pts), oracle_mod.skyline_sfs(pts))
+    u = datagen.quantise_u16(datagen.anticorrelated(200_000, 6, seed=9))
+    assert np.array_equal(oracle_mod.skyline_kdtree(u), oracle_mod.skyline_sfs(u))
+
+
+def test_kdtree_detects_a_planted_dominator(oracle_mod):
+    """A single point planted just below one skyline point in every dimension
+    removes it and nothing else that it does not dominate."""
+    pts = datagen.anticorrelated(50_000, 6, seed=3)
+    sky = oracle_mod.skyline_kdtree(pts)
+    victim = int(sky[len(sky) // 2])
+    planted = np.nextafter(pts[victim], np.float32(-1.0))[None, :]
+    more = np.concatenate([pts, planted])
+    got = oracle_mod.skyline_kdtree(more)
+    assert victim not in set(got.tolist()) and 50_000 in set(got.tolist())
+    assert np.array_equal(got, oracle_mod.skyline_bruteforce(more))
