@@ -184,6 +184,16 @@ int skycell_set_refine_form(int32_t form);
 int skycell_set_wave_parts(int32_t parts);
 
 /*
+ * Sampling gate of the pivot pre-filter (skycell_compute_with_pivots,
+ * skycell_compute_pivoted) for all later calls in the process: 1 (the default)
+ * screens a sample first and skips the full pass when the pivots remove fewer
+ * than 1 in 100 of its points; 0 always runs the full pass, so that every point
+ * of a surviving cell that a pivot dominates is removed.  The skyline never
+ * depends on it.  Returns SKYCELL_E_INVAL unless on is 0 or 1.
+ */
+int skycell_set_pivot_gate(int32_t on);
+
+/*
  * Byte offsets of the workspace's sub-buffers for (n, d, grid_res) (grid_res 0 =
  * autotuned), for tests and tools that inspect intermediate results of a
  * skycell_compute_ws call.  offsets[0..count) receives, in this order:

@@ -171,16 +171,3 @@ def dominated_by_any(points, pivots, chunk=512):
         lt = (v[None, :, :] < qq).any(axis=2)
         out[s:s + chunk] = (le & lt).any(axis=1)
     return out
-
-
-def pivot_gate(points, survive, pivots, nsample=16384):
-    """Whether the pivot pre-filter runs: points i = j * (n // m), j < m, with
-    m = min(n, nsample), are sampled; among the sampled points of surviving
-    cells (`survive`, a boolean mask), the pass runs when at least one in 100
-    is dominated by a pivot (or when none was sampled)."""
-    n = np.asarray(points).shape[0]
-    m = min(n, nsample)
-    idx = np.arange(m, dtype=np.int64) * (n // m)
-    cand = idx[np.asarray(survive)[idx]]
-    hit = int(dominated_by_any(np.asarray(points)[cand], pivots).sum()) if cand.size else 0
-    return hit * 100 >= cand.size

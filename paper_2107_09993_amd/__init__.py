@@ -60,6 +60,7 @@ def lib():
     L.skycell_load_tuning.argtypes = [ctypes.c_char_p]
     L.skycell_set_refine_form.argtypes = [i32]
     L.skycell_set_wave_parts.argtypes = [i32]
+    L.skycell_set_pivot_gate.argtypes = [i32]
     L.skycell_workspace_layout.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz), i32]
     L.skycell_profile_enable.argtypes = [i32]
     L.skycell_profile_read.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
@@ -88,7 +89,7 @@ def lib():
     L.skycell_last_error.restype = ctypes.c_char_p
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
                  "skycell_compute_ws", "skycell_compute_static", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
-                 "skycell_set_wave_parts",
+                 "skycell_set_wave_parts", "skycell_set_pivot_gate",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
                  "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
                  "skycell_plan_destroy", "skycell_mlp_num_params", "skycell_mlp_create",
@@ -158,6 +159,13 @@ def set_refine_form(form):
 def set_wave_parts(parts):
     """Waves per work item of the wave-form refine for later calls (0 = per call)."""
     _check(lib().skycell_set_wave_parts(int(parts)))
+
+
+def set_pivot_gate(on):
+    """Sampling gate of the pivot pre-filter for later calls: True (default)
+    skips the full pass when a sample shows almost nothing to remove; False
+    always screens every point of a surviving cell against the pivots."""
+    _check(lib().skycell_set_pivot_gate(1 if on else 0))
 
 
 def load_tuning(path):

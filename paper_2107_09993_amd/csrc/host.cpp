@@ -186,6 +186,9 @@ static int refine_form(int64_t n, int d, int g, int dtype)
 // chip idles.
 static std::atomic<int> g_parts_override{-2};  // -2 unread, 0 none, else the count
 
+// Sampling gate of the pivot pre-filter (skycell_set_pivot_gate): 1 = on.
+static std::atomic<int> g_pivot_gate{1};
+
 static int wave_parts(int64_t n, int d, int g, int dtype)
 {
     int ov = g_parts_override.load();
@@ -407,7 +410,8 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
     if (pivots) {
         SKYCELL_HIP_CHECK(launch_pivot_gather((const float *)points, (uint32_t)n, d, piv->idx, piv->k, piv->ps,
                                               ws.ctr, st));
-        SKYCELL_HIP_CHECK(launch_pivot_prune((const float *)points, (uint32_t)n, gd, ws, piv->ps, piv->k, stats, st));
+        SKYCELL_HIP_CHECK(launch_pivot_prune((const float *)points, (uint32_t)n, gd, ws, piv->ps, piv->k, stats,
+                                             g_pivot_gate.load() != 0, st));
     }
     SKYCELL_PROF(2);
     SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st, pivots));
@@ -512,6 +516,13 @@ int skycell_set_refine_form(int32_t form)
 {
     if (form < -1 || form > 1) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0 or 1", form);
     g_form_override.store(form);
+    return ok();
+}
+
+int skycell_set_pivot_gate(int32_t on)
+{
+    if (on != 0 && on != 1) return fail(SKYCELL_E_INVAL, "on = %d is not 0 or 1", on);
+    g_pivot_gate.store(on);
     return ok();
 }
 

@@ -79,7 +79,9 @@ hipError_t launch_topk(const float *scores, uint32_t n, uint32_t k, int32_t *out
                        hipStream_t st);
 hipError_t launch_pivot_gather(const float *pts, uint32_t n, int d, const int32_t *idx, uint32_t k,
                                const PivotScratch &ps, uint32_t *ctr, hipStream_t st);
+// gated: screen a sample first and run the full pass only when the pivots
+// remove at least 1 in 100 of its points of surviving cells
 hipError_t launch_pivot_prune(const float *pts, uint32_t n, const GridDesc &gd, const Workspace &ws,
-                              const PivotScratch &ps, uint32_t k, uint64_t *stats, hipStream_t st);
+                              const PivotScratch &ps, uint32_t k, uint64_t *stats, bool gated, hipStream_t st);
 
 }  // namespace skycell

@@ -363,12 +363,13 @@ __global__ __launch_bounds__(kPruneThreads) void k_pivot_prune(const float *__re
                                                                uint32_t *__restrict__ rank,
                                                                uint32_t *__restrict__ cnt,
                                                                const uint32_t *__restrict__ ctr,
-                                                               uint64_t *__restrict__ stats)
+                                                               uint64_t *__restrict__ stats, int gated)
 {
     __shared__ uint64_t s_f[kPivotChunk * fine_words(D)];
     const uint32_t i = blockIdx.x * kPruneThreads + threadIdx.x;
-    // the sample decides for the whole grid (the same value in every thread)
-    const bool use = (uint64_t)ctr[kCtrPivHit] * 100u >= (uint64_t)ctr[kCtrPivSampled];
+    // the sample decides for the whole grid (the same value in every thread);
+    // without the gate every point of a surviving cell is screened
+    const bool use = !gated || (uint64_t)ctr[kCtrPivHit] * 100u >= (uint64_t)ctr[kCtrPivSampled];
     uint32_t x = 0u;
     bool cand = false;
     if (i < n) {
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(kPruneThreads) void k_pivot_prune(const float *__re
 }
 
 hipError_t launch_pivot_prune(const float *pts, uint32_t n, const GridDesc &gd, const Workspace &ws,
-                              const PivotScratch &ps, uint32_t k, uint64_t *stats, hipStream_t st)
+                              const PivotScratch &ps, uint32_t k, uint64_t *stats, bool gated, hipStream_t st)
 {
     unsigned zb = (gd.cells + 255u) / 256u;
     if (zb > 4096) zb = 4096;
@@ -400,12 +401,14 @@ hipError_t launch_pivot_prune(const float *pts, uint32_t n, const GridDesc &gd, 
     switch (gd.d) {
 #define SKYCELL_PRUNE_CASE(DD)                                                                                  \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL(k_pivot_sample<DD>, sgrid, dim3(kPruneThreads), 0, st, pts, n, stride, nsample,      \
-                           (const uint32_t *)ws.cell_of, (const uint64_t *)ws.rec, (const uint32_t *)ps.pkeys,  \
-                           (const uint64_t *)ps.pfine, k, ws.ctr);                                             \
+        if (gated)                                                                                              \
+            hipLaunchKernelGGL(k_pivot_sample<DD>, sgrid, dim3(kPruneThreads), 0, st, pts, n, stride, nsample,  \
+                               (const uint32_t *)ws.cell_of, (const uint64_t *)ws.rec,                          \
+                               (const uint32_t *)ps.pkeys, (const uint64_t *)ps.pfine, k, ws.ctr);              \
         hipLaunchKernelGGL(k_pivot_prune<DD>, grid, dim3(kPruneThreads), 0, st, pts, n,                         \
                            (const uint32_t *)ws.cell_of, (const uint64_t *)ws.rec, (const uint32_t *)ps.pkeys,  \
-                           (const uint64_t *)ps.pfine, k, ws.rank, ws.cnt, (const uint32_t *)ws.ctr, stats);   \
+                           (const uint64_t *)ps.pfine, k, ws.rank, ws.cnt, (const uint32_t *)ws.ctr, stats,    \
+                           gated ? 1 : 0);                                                                      \
         break;
         SKYCELL_PRUNE_CASE(1)
         SKYCELL_PRUNE_CASE(2)

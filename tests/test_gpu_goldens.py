@@ -94,7 +94,7 @@ def test_single_workload_full(inputs, name):
     assert_golden(x, run_plain(x, grid_res=8 if name == "C1" else 0), e, name)
 
 
-@pytest.mark.parametrize("name,grid", [("C2-anti", 4), ("C2-ind", 16), ("H", 6), ("C3", 8)])
+@pytest.mark.parametrize("name,grid", [("C2-anti", 4), ("C2-ind", 6), ("H", 6), ("C3", 8)])
 def test_single_workload_other_grids(inputs, name, grid):
     e = GOLDEN["single"][name]
     x = inputs(name)

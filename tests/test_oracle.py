@@ -420,3 +420,129 @@ def test_kdtree_detects_a_planted_dominator(oracle_mod):
     got = oracle_mod.skyline_kdtree(more)
     assert victim not in set(got.tolist()) and 50_000 in set(got.tolist())
     assert np.array_equal(got, oracle_mod.skyline_bruteforce(more))
+
+
+# ---------------------------------------------------------------- Algorithm 3
+def _brute_cell_types(cells, nonempty):
+    """Definitions 3-4 by brute force over explicit cells: per row,
+    'dominated' (a non-empty cell is below in every dimension), 'key'
+    (non-empty, no other non-empty cell <= it), else 'other'."""
+    ne = [tuple(c) for c, e in zip(cells.tolist(), nonempty.tolist()) if e]
+    out = []
+    for c, e in zip(cells.tolist(), nonempty.tolist()):
+        c = tuple(c)
+        if any(C.dominates_cell(a, c) for a in ne):
+            out.append("dominated")
+        elif e and not any(a != c and all(x <= y for x, y in zip(a, c)) for a in ne):
+            out.append("key")
+        else:
+            out.append("other")
+    return out
+
+
+def test_alg3_counterexample_two_minimal_cells():
+    """Section V-B, Theorem 2 does not hold in general: with the non-empty cells
+    (c0, c1) = (1,0), (0,1), (2,1) of a 3 x 3 grid, (1,0) dominates (2,1), but
+    the tree's single pointer reaches (2,1) through (0,1), which only partially
+    dominates it, so Algorithm 3 reports a candidate cell (Definition 3 says
+    dominated).  With (1,2) in place of (2,1) the dominator is the one the tree
+    keeps and the verdict is right."""
+    ne = np.ones(3, bool)
+    cells = np.array([(1, 0), (0, 1), (2, 1)])
+    assert list(C.classify_parallel(cells, ne)) == ["key", "key", "candidate"]
+    assert C.dominated_cells([(1, 0), (0, 1), (2, 1)]) == {(2, 1)}
+    cells = np.array([(0, 1), (1, 0), (1, 2)])
+    assert list(C.classify_parallel(cells, ne)) == ["key", "key", "dominated"]
+
+
+def test_alg3_follows_the_tree_by_hand():
+    """A worked run of the two sweeps on four cells in two dimensions, traced by
+    hand from Algorithm 3: sorted order (dimension 1 major) (0,0) (1,0) (0,1)
+    (1,1); (0,0) is the only non-empty cell and 2-dominates all others."""
+    cells = np.array([(1, 1), (0, 1), (1, 0), (0, 0)])
+    ne = np.array([False, False, False, True])
+    o, l = C.shrink_key_cells_parallel(cells, ne)
+    assert o.tolist() == [3, 2, 1, 0]          # leaves in sorted order
+    assert l.tolist() == [3, 3, 3, 3]          # every l points at (0,0)
+    assert list(C.classify_parallel(cells, ne)) == ["dominated", "candidate", "candidate", "key"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_alg3_verdicts_are_one_sided(seed):
+    """On random occupancies (d = 2..4, every cell a leaf or only the non-empty
+    ones): a 'dominated' verdict is always right (the pointer dominates the
+    cell), every key cell of Definition 4 comes out as a key cell, and a
+    non-empty cell is never left unclassified."""
+    rng = np.random.default_rng(seed)
+    for trial in range(40):
+        d = int(rng.integers(2, 5))
+        g = int(rng.integers(2, 6))
+        allc = np.array(list(itertools.product(range(g), repeat=d)))
+        occ = rng.random(len(allc)) < rng.choice([0.05, 0.2, 0.5])
+        if trial % 2:
+            cells, ne = allc[occ], occ[occ]
+        else:
+            cells, ne = allc, occ
+        if cells.shape[0] == 0:
+            continue
+        got = C.classify_parallel(cells, ne)
+        want = _brute_cell_types(cells, ne)
+        for gv, wv, e in zip(got, want, ne):
+            if gv == "dominated":
+                assert wv == "dominated"
+            if wv == "key":
+                assert gv == "key"
+            if e:
+                assert gv != "irrelevant"
+
+
+def test_alg3_exact_on_two_dimensional_chains():
+    """In two dimensions (one rotation), with only non-empty cells as leaves, and
+    where every cell has a single minimal non-empty cell below it (the non-empty
+    cells form a chain), Theorem 2 holds: the verdicts equal the definitions.
+    (Empty leaves break it even then: a subtree whose last cell is empty and
+    not 2-dominated inside it passes that empty cell up as its pointer.)"""
+    rng = np.random.default_rng(7)
+    for trial in range(30):
+        g = 7
+        steps = rng.integers(0, 2, size=(g, 2))
+        chain = np.unique(np.minimum(np.cumsum(steps, axis=0), g - 1), axis=0)
+        allc = np.array(list(itertools.product(range(g), repeat=2)))
+        ne = np.array([any((c == ch).all() for ch in chain) for c in allc])
+        for cells, nn in ((allc[ne], ne[ne]),):
+            got = C.classify_parallel(cells, nn)
+            want = _brute_cell_types(cells, nn)
+            for gv, wv in zip(got, want):
+                assert (gv == "dominated") == (wv == "dominated")
+                assert (gv == "key") == (wv == "key")
+
+
+def test_alg3_rotations_do_not_compose_through_empty_leaves():
+    """A second departure, in three dimensions: with all eight cells of a
+    2 x 2 x 2 split as leaves and only (0,0,0) and (1,1,1) non-empty, each
+    rotation's 2-domination test compares the pointers themselves, which never
+    agree with (1,1,1) in the d - 2 dimensions the test holds fixed, so
+    Algorithm 3 reports (1,1,1) as a key cell although (0,0,0) dominates it."""
+    allc = np.array(list(itertools.product(range(2), repeat=3)))
+    ne = np.array([tuple(c) in ((0, 0, 0), (1, 1, 1)) for c in allc.tolist()])
+    got = dict(zip(map(tuple, allc.tolist()), C.classify_parallel(allc, ne)))
+    assert got[(1, 1, 1)] == "key"
+    assert got[(0, 0, 0)] == "key"
+    assert C.dominated_cells([(0, 0, 0), (1, 1, 1)]) == {(1, 1, 1)}
+
+
+def test_alg3_layers_keep_every_survivor():
+    """The layer loop of Algorithm 1 with Algorithm 3: at every layer, each
+    non-empty cell that Definition 3 keeps is a key or candidate cell (the
+    errors of Algorithm 3 only keep extra cells)."""
+    rng = np.random.default_rng(3)
+    for d, rho in ((2, 4), (3, 3), (4, 2)):
+        x = rng.random((300, d)).astype(np.float32)
+        def layer_cells(i):
+            return {tuple(c) for c in np.floor(x.astype(np.float64) * (1 << i)).astype(int).tolist()}
+        res = C.layers_parallel(layer_cells, rho, d)
+        for i in range(1, rho + 1):
+            ne = layer_cells(i)
+            surv = ne - C.dominated_cells(ne)
+            kept = {c for c, t in res[i].items() if c in ne}
+            assert surv <= kept, (d, i)

@@ -222,15 +222,3 @@ def test_all_points_as_pivots_remove_exactly_the_non_skyline(oracle_mod):
     removed = L.dominated_by_any(x, x)
     mask = np.ones(3000, bool); mask[sky] = False
     assert np.array_equal(removed, mask)
-
-
-def test_pivot_gate_rule():
-    x = datagen.generate("independent", 50_000, 3, 11)
-    surv = np.ones(50_000, bool)
-    # the all-zero point dominates every other point: the gate opens
-    piv = np.zeros((1, 3), np.float32)
-    assert L.pivot_gate(x, surv, piv)
-    # a pivot above everything removes nothing: the gate stays closed
-    assert not L.pivot_gate(x, surv, np.full((1, 3), 2.0, np.float32))
-    # nothing sampled (no surviving cell): the pass runs
-    assert L.pivot_gate(x, np.zeros(50_000, bool), np.full((1, 3), 2.0, np.float32))
