@@ -9,8 +9,11 @@ the skyline size back.  The workload is n = 10^7 anti-correlated points in d = 8
 Prints one JSON line.  `value` is input points per second over the K timed
 steps (wall clock between two device synchronisations).  `roofline` describes
 the dominant kernel (the refine), timed with hipEvents recorded on the launch
-stream during the timed steps; `cpu_baseline` is the CPU oracle timed on a
-bounded prefix of the same data.
+stream during the timed steps; `cpu_baseline` is the CPU oracle (its k-d tree
+orthant test) timed on the same data.  `configs` times the other
+single-instance workloads the same way (points/s, dominance tests/s, bandwidth
+of the algorithmic bytes); `batched` and `learned` are the batched and
+learned-proposer workloads.  Progress lines go to stderr.
 """
 import argparse
 import hashlib
@@ -30,6 +33,14 @@ PEAK_ALU_OPS = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12
 
 
+def progress(msg):
+    """One line per finished leg on stderr, so a long run shows where it is."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+T_START = time.perf_counter()
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,8 +51,12 @@ def parse():
     ap.add_argument("--dist", default="anticorrelated")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=250_000,
-                    help="prefix size for the CPU oracle baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="points of the workload for the CPU oracle baseline (-1 = all of "
+                         "them, 0 = skip)")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="also time the other single-instance workloads (1 = yes)")
+    ap.add_argument("--config-steps", type=int, default=10)
     ap.add_argument("--batched-count", type=int, default=4096,
                     help="instances of the batched workload (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=3)
@@ -115,6 +130,81 @@ def batched_bench(count, steps, dev):
                         "independent/correlated/anti-correlated per instance, seeds 1e6+b"}
 
 
+# The other single-instance workloads: name -> (distribution, n, d, seed, uint16 with
+# 10 value bits, grid or 0 for the library's choice)
+CONFIGS = {
+    "C1 independent n=1e4 d=4 g=8": ("independent", 10_000, 4, 0, False, 8),
+    "C2 independent n=1e6 d=8": ("independent", 1_000_000, 8, 0, False, 0),
+    "C2 correlated n=1e6 d=8": ("correlated", 1_000_000, 8, 0, False, 0),
+    "C2 anti-correlated n=1e6 d=8": ("anticorrelated", 1_000_000, 8, 0, False, 0),
+    "C3 anti-correlated uint16 n=1e7 d=6": ("anticorrelated", 10_000_000, 6, 0, True, 0),
+}
+
+
+def single_bench(x, grid, steps, warmup, dev, value_bits=10):
+    """Times `steps` calls of the whole path on resident data (one host sync per
+    call, as in the headline); returns points/s, tests/s and bandwidth."""
+    import numpy as np
+    import torch
+    import paper_2107_09993_amd as sky
+    n, d = x.shape
+    dtype = "u16" if x.dtype == np.uint16 else "f32"
+    soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
+    g = grid if grid else sky.choose_grid(n, d, sky.DTYPE_U16 if dtype == "u16" else sky.DTYPE_F32)
+    probe = sky.Skyline(n, d, dtype=dtype, grid_res=g, value_bits=value_bits, device=dev, stats=True)
+    probe.run(soa)
+    count = int(probe.result().numel())
+    st = probe.stats_dict()
+    del probe
+    sk = sky.Skyline(n, d, dtype=dtype, grid_res=g, value_bits=value_bits, device=dev)
+    for _ in range(warmup):
+        sk.run(soa)
+        sk.result()
+    sky.profile_enable(True)
+    phase_sum = dict.fromkeys(sky.PHASE_NAMES, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sk.run(soa)
+        c = int(sk.out_count.item())
+        for k, v in sky.profile_read().items():
+            phase_sum[k] += v
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sky.profile_enable(False)
+    if c != count:
+        raise RuntimeError("skyline size changed between calls: %d vs %d" % (c, count))
+    del sk, soa
+    torch.cuda.empty_cache()
+    ms = 1e3 * wall / steps
+    phases = {k: v / steps for k, v in phase_sum.items()}
+    cells = (1 << (max(1, (g - 1).bit_length()) * d)) if g > 1 else 1
+    eb = 2 if dtype == "u16" else 4
+    pb = phase_bytes(n, d, cells, st)
+    pb["quantize_hist"] += n * d * (eb - 4)
+    pb["scatter"] += n * d * (eb - 4)
+    total = sum(pb.values())
+    return {"points_per_s": n / (wall / steps), "ms_per_call": ms, "grid_res": g, "dtype": dtype,
+            "skyline": count, "survivor_points": st["survivor_points"],
+            "dominance_tests_per_s": st["pair_tests"] / (ms * 1e-3),
+            "phases_ms": phases,
+            "algorithmic_bytes": total,
+            "hbm_gbs": total / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": total / (ms * 1e-3) / PEAK_HBM}
+
+
+def configs_bench(steps, dev):
+    from paper_2107_09993_amd import datagen
+    out = {}
+    for name, (dist, n, d, seed, u16, grid) in CONFIGS.items():
+        x = datagen.generate(dist, n, d, seed)
+        if u16:
+            x = datagen.quantise_u16(x)
+        out[name] = single_bench(x, grid, steps, 2, dev)
+        progress("config %s: %.3g points/s" % (name, out[name]["points_per_s"]))
+    return out
+
+
 def learned_bench(n, dev):
     """Pivoted vs plain skyline with the committed networks, k = 4096 pivots,
     with random and smallest-coordinate-sum pivots for comparison: the learned
@@ -139,16 +229,19 @@ def learned_bench(n, dev):
 
 
 def cpu_baseline(x_host, sample):
+    """The CPU oracle's k-d tree orthant test (O3) on the first `sample` points
+    of the workload (all of them by default), on every host thread."""
     import oracle
-    n = min(sample, x_host.shape[0])
-    xs = x_host[:n].copy()
+    n = x_host.shape[0] if sample < 0 else min(sample, x_host.shape[0])
+    xs = x_host[:n]
     threads = oracle.default_threads()
     t0 = time.perf_counter()
-    sky = oracle.skyline_sfs(xs, nthreads=threads)
+    sky = oracle.skyline_kdtree(xs, nthreads=threads)
     dt = time.perf_counter() - t0
+    what = "all %d points" % n if n == x_host.shape[0] else "the first %d points" % n
     return {"value": n / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": "sort-first skyline oracle on the first %d points of the same data "
-                      "(%d skyline points, %.1f s)" % (n, len(sky), dt)}
+            "sample": "k-d tree orthant oracle (O3) on %s of the same data "
+                      "(%d skyline points, %.1f s)" % (what, len(sky), dt)}
 
 
 def phase_bytes(n, d, cells, st):
@@ -198,6 +291,7 @@ def main():
         del src, dst
     x = datagen.generate(a.dist, a.n, a.d, a.seed)
     soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
+    progress("headline input generated and resident: %s n=%d d=%d" % (a.dist, a.n, a.d))
     g = a.grid if a.grid else sky.choose_grid(a.n, a.d)
 
     # one call with counters for the algorithmic work figures
@@ -231,6 +325,7 @@ def main():
         sys.exit(1)
 
     ms_per_step = 1e3 * wall / a.steps
+    progress("headline: %d steps, %.3f ms per step" % (a.steps, 1e3 * wall / a.steps))
     phases = {k: v / a.steps for k, v in phase_sum.items()}
     value = a.n / (wall / a.steps)
 
@@ -268,15 +363,22 @@ def main():
            "dominance_tests_per_s": st["pair_tests"] / (ms_per_step * 1e-3),
            "counters": st,
            "roofline": roof}
+    del sk, soa
+    torch.cuda.empty_cache()
+    if a.configs:
+        out["configs"] = configs_bench(a.config_steps, dev)
     if a.batched_count > 0:
-        del sk
         torch.cuda.empty_cache()
         out["batched"] = batched_bench(a.batched_count, a.batched_steps, dev)
+        progress("batched: %.1f instances/s" % out["batched"]["value"])
     if a.learned_n > 0:
         torch.cuda.empty_cache()
         out["learned"] = learned_bench(a.learned_n, dev)
-    if a.cpu_sample > 0:
+        progress("learned leg done")
+    if a.cpu_sample != 0:
         out["cpu_baseline"] = cpu_baseline(x, a.cpu_sample)
+        progress("cpu baseline: %.3g points/s on %d threads" % (out["cpu_baseline"]["value"],
+                                                                out["cpu_baseline"]["cores"]))
     print(json.dumps(out), flush=True)
 
 

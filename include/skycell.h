@@ -123,6 +123,28 @@ int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d,
                        uint64_t *stats, void *stream);
 
 /*
+ * Exact skyline with a two-layer grid for grids finer than a dense cell table
+ * allows (Section III: layer rho has 2^rho columns; a non-empty cell can
+ * survive only inside a surviving cell of the layer above).  The base layer,
+ * 2^(rho-1) columns, is the dense grid of skycell_compute (histogram, lower
+ * closure, records, scatter, refine); the fine layer, 2^rho columns (Equation
+ * 1), is kept as one occupancy bit per cell, and its Definition 3 prune is
+ * exact: for every surviving base cell, a walk of its lower cone finds which
+ * of its fine cells a non-empty fine cell dominates.  Points of dominated fine
+ * cells are dropped before the refine.  Same arguments and results as
+ * skycell_compute_ws with grid_res replaced by rho; 2 <= d <= 8, rho >= 2,
+ * (rho-1)*d <= 26 and rho*d <= 32 (d = 8: g = 16 is 2^32 fine cells).  The
+ * library owns the workspace and the two fine bitmaps (2^(rho d) bits each).
+ * stats (NULL or device uint64 [SKYCELL_NUM_STATS]): the cell counters count
+ * fine cells (non-empty; not dominated inside surviving base cells), the
+ * point and refine counters the base path; SKYCELL_STAT_GRID_RES is the base
+ * grid.
+ */
+int skycell_compute_layered(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t rho,
+                            int32_t value_bits, int32_t *out_idx, int32_t *out_count, uint64_t *stats,
+                            void *stream);
+
+/*
  * For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): skycell_compute_ws
  * without a workspace argument.  Its scratch is a fixed array of
@@ -192,6 +214,37 @@ int skycell_set_wave_parts(int32_t parts);
  * depends on it.  Returns SKYCELL_E_INVAL unless on is 0 or 1.
  */
 int skycell_set_pivot_gate(int32_t on);
+
+/*
+ * Cell prune of skycell_compute, skycell_compute_u16 and skycell_compute_ws for
+ * all later calls in the process (the _static, batched and pivoted forms
+ * always use 0).  With form 1, skycell_compute_ws also allocates the tree's
+ * scratch (library-owned, kept per device and stream), so this measurement
+ * mode is not for callers that must not allocate:
+ *   0  (default) Definition 3 by a prefix-OR of the occupancy along each
+ *      dimension: a non-empty cell survives iff no non-empty cell has a
+ *      smaller column in every dimension;
+ *   1  the paper's parallel ShrinkKeyCells (Section V-B, Algorithm 3) run
+ *      layer by layer as in Algorithm 1 (layer i has 2^i columns; layer i+1's
+ *      leaves are the 2^d children of layer i's key and candidate cells), for
+ *      grids of g = 2^rho columns (other grids keep form 0).  Its verdicts
+ *      are one-sided (a cell it calls dominated is dominated, but it keeps some
+ *      dominated cells: Theorem 2 does not hold in general), so it keeps a
+ *      superset of form 0's survivors; the skyline is the same.
+ * Returns SKYCELL_E_INVAL unless form is 0 or 1.
+ */
+int skycell_set_cell_prune(int32_t form);
+
+/*
+ * The tree form's layers on their own, for tests and measurements: the points'
+ * occupancy at g = 2^rho (1 <= rho, rho * d <= 26; Equation 1 per layer), then
+ * Algorithm 3 for layers 1..rho.  key_out and cand_out (device uint64 bitmaps)
+ * receive, for every layer j = 1..rho in turn, one bit per cell of the layer
+ * (Morton index: bit b of column k at index bit b*d + k; ceil(2^(j d) / 64)
+ * words per layer): key cells, and key plus candidate cells (Theorem 2).
+ */
+int skycell_shrink_tree(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t rho, int32_t value_bits,
+                        uint64_t *key_out, uint64_t *cand_out, void *stream);
 
 /*
  * Byte offsets of the workspace's sub-buffers for (n, d, grid_res) (grid_res 0 =
@@ -280,6 +333,90 @@ int skycell_batched_run(skycell_plan_t plan, const void *points, int32_t *out_id
 
 /* Waits for the device, then frees the plan's memory and graph. */
 int skycell_plan_destroy(skycell_plan_t plan);
+
+/*
+ * ------------------------------------------------------------------------
+ * Incremental maintenance under inserts and deletes.
+ *
+ * The paper holds (Section I; Section VII-B3, dynamic scenarios) that SkyCell
+ * needs no pre-computation, so updates do not invalidate anything it keeps.
+ * A skycell_dyn_t keeps a point set in library-owned device memory with each
+ * point's skyline flag (Definition 2 over the live points) and updates it per
+ * batch by recomputing only the points the batch can change:
+ *   insert B: sky(P + B) = sky(S + B) with S the current skyline (a dominated
+ *             point stays dominated when points are added);
+ *   delete D: sky(P - D) = sky((S - D) + R), R = the live non-skyline points
+ *             that some deleted skyline point is <= in every dimension.
+ * The recompute is the whole single-instance path on the gathered points.
+ * Ids are insertion positions 0, 1, 2, ... and are never reused.  Each update
+ * synchronises the stream (it reads candidate counts back) and returns once
+ * the flags are final.  Calls on one handle are serialised by the library.
+ */
+typedef struct skycell_dyn *skycell_dyn_t;
+
+/* capacity: ids available over the handle's life (1 <= capacity < 2^31).
+ * dtype SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16 (value_bits as for
+ * skycell_compute_u16; ignored for F32).  Allocates capacity * (2 d esize + 11)
+ * bytes on the current device; the recompute's workspace grows on demand. */
+int skycell_dyn_create(int32_t d, int32_t dtype, int64_t capacity, int32_t value_bits, skycell_dyn_t *out);
+
+/* Append m points (device SoA [d][m], the handle's dtype) as ids first_id ..
+ * first_id + m - 1 (*first_id may be NULL).  SKYCELL_E_NOMEM when the capacity
+ * would be exceeded, SKYCELL_E_NAN when the batch holds a NaN; in both cases
+ * nothing is inserted. */
+int skycell_dyn_insert(skycell_dyn_t h, const void *points, int64_t m, int64_t *first_id, void *stream);
+
+/* Delete the ids in ids[0..m) (device int32).  Deleted and repeated ids are
+ * ignored; an id outside [0, ids used) makes it return SKYCELL_E_RANGE after
+ * the valid ids of the batch were deleted and the skyline updated. */
+int skycell_dyn_delete(skycell_dyn_t h, const int32_t *ids, int64_t m, void *stream);
+
+/* The current skyline as ascending ids (device int32, capacity >= ids used)
+ * and its size (device int32), enqueued on the stream. */
+int skycell_dyn_skyline(skycell_dyn_t h, int32_t *out_idx, int32_t *out_count, void *stream);
+
+/* Ids handed out so far, and how many points the last update recomputed. */
+int skycell_dyn_size(skycell_dyn_t h, int64_t *ids_used, int64_t *last_candidates);
+
+/* Waits for the device, then frees the handle's memory. */
+int skycell_dyn_destroy(skycell_dyn_t h);
+
+/*
+ * ------------------------------------------------------------------------
+ * Quadrant (dynamic-origin) skyline queries, Section VII-B3.
+ *
+ * A query point o is taken as the new origin and only the points of its
+ * top-right quadrant Q(o) = { p : p[k] >= o[k] for every k } (closed, compared
+ * exactly; -0.0 = +0.0) take part: the answer to the query is the skyline of
+ * Q(o) (Definitions 1-2), as ascending indices into the data set.  Many
+ * queries on one resident data set run as the instances of one batched plan
+ * (skycell_batched_*): the create call measures |Q(o)| for every query and
+ * lays the plan out; each run gathers the quadrants, launches the plan's graph
+ * once, and writes every query's skyline.
+ */
+typedef struct skycell_quad *skycell_quad_t;
+
+/* points: device SoA [d][n] (dtype F32 or U16; value_bits as for
+ * skycell_compute_u16).  origins: device SoA [d][nq] of the same dtype
+ * (1 <= nq <= 4,194,240).  Counts the quadrants (synchronises the stream) and
+ * allocates the plan; the quadrants together must hold fewer than 2^31 points
+ * (else SKYCELL_E_RANGE).  A NaN origin gives SKYCELL_E_NAN. */
+int skycell_quadrant_create(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t value_bits,
+                            const void *origins, int32_t nq, skycell_quad_t *out, void *stream);
+
+/* out_off[0..nq]: query q's skyline goes to out_idx[out_off[q] ..] (room for
+ * |Q(o_q)| indices); out_off[nq] is the capacity out_idx needs. */
+int skycell_quadrant_offsets(skycell_quad_t h, int64_t *out_off);
+
+/* Answer every query for the same points and origins the handle was created
+ * with: out_idx (device int32, capacity out_off[nq]) receives at out_off[q]
+ * the ascending skyline of query q, out_count (device int32 [nq]) its size (or
+ * SKYCELL_E_NAN when Q(o_q) holds a NaN).  The first run captures the graph. */
+int skycell_quadrant_run(skycell_quad_t h, const void *points, const void *origins, int32_t *out_idx,
+                         int32_t *out_count, void *stream);
+
+/* Waits for the device, then frees the handle and its plan. */
+int skycell_quadrant_destroy(skycell_quad_t h);
 
 /*
  * ------------------------------------------------------------------------

@@ -61,6 +61,8 @@ def lib():
     L.skycell_set_refine_form.argtypes = [i32]
     L.skycell_set_wave_parts.argtypes = [i32]
     L.skycell_set_pivot_gate.argtypes = [i32]
+    L.skycell_set_cell_prune.argtypes = [i32]
+    L.skycell_shrink_tree.argtypes = [p, i32, i64, i32, i32, i32, p, p, p]
     L.skycell_workspace_layout.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz), i32]
     L.skycell_profile_enable.argtypes = [i32]
     L.skycell_profile_read.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
@@ -85,11 +87,22 @@ def lib():
     L.skycell_topk.argtypes = [p, i64, i32, p, p]
     L.skycell_compute_with_pivots.argtypes = [p, i64, i32, i32, p, i32, p, p, p, p]
     L.skycell_compute_pivoted.argtypes = [p, i64, i32, i32, p, i32, p, p, p, p]
+    L.skycell_dyn_create.argtypes = [i32, i32, i64, i32, ctypes.POINTER(p)]
+    L.skycell_dyn_insert.argtypes = [p, p, i64, ctypes.POINTER(i64), p]
+    L.skycell_dyn_delete.argtypes = [p, p, i64, p]
+    L.skycell_dyn_skyline.argtypes = [p, p, p, p]
+    L.skycell_dyn_size.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.skycell_dyn_destroy.argtypes = [p]
+    L.skycell_quadrant_create.argtypes = [p, i32, i64, i32, i32, p, i32, ctypes.POINTER(p), p]
+    L.skycell_quadrant_offsets.argtypes = [p, p]
+    L.skycell_quadrant_run.argtypes = [p, p, p, p, p, p]
+    L.skycell_quadrant_destroy.argtypes = [p]
     L.skycell_last_error.argtypes = []
     L.skycell_last_error.restype = ctypes.c_char_p
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
                  "skycell_compute_ws", "skycell_compute_static", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
-                 "skycell_set_wave_parts", "skycell_set_pivot_gate",
+                 "skycell_set_wave_parts", "skycell_set_pivot_gate", "skycell_set_cell_prune",
+                 "skycell_shrink_tree",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
                  "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
                  "skycell_plan_destroy", "skycell_mlp_num_params", "skycell_mlp_create",
@@ -97,7 +110,10 @@ def lib():
                  "skycell_mlp_get_grads", "skycell_mlp_set_grads", "skycell_mlp_score",
                  "skycell_mlp_backward", "skycell_mlp_adam_step", "skycell_mlp_train_step",
                  "skycell_mlp_save", "skycell_mlp_load", "skycell_skyline_labels", "skycell_topk",
-                 "skycell_compute_with_pivots", "skycell_compute_pivoted"):
+                 "skycell_compute_with_pivots", "skycell_compute_pivoted",
+                 "skycell_dyn_create", "skycell_dyn_insert", "skycell_dyn_delete", "skycell_dyn_skyline",
+                 "skycell_dyn_size", "skycell_dyn_destroy", "skycell_quadrant_create",
+                 "skycell_quadrant_offsets", "skycell_quadrant_run", "skycell_quadrant_destroy"):
         getattr(L, name).restype = i32
     _lib = L
     table = os.path.join(HERE, "tuning", "mi355x.txt")
@@ -148,7 +164,7 @@ def workspace_layout(n, d, grid_res=0, dtype=DTYPE_F32):
     return list(offs)
 
 
-REFINE_FORMS = {"auto": -1, "lane": 0, "wave": 1}
+REFINE_FORMS = {"auto": -1, "lane": 0, "wave": 1, "tile": 2}
 
 
 def set_refine_form(form):
@@ -166,6 +182,39 @@ def set_pivot_gate(on):
     skips the full pass when a sample shows almost nothing to remove; False
     always screens every point of a surviving cell against the pivots."""
     _check(lib().skycell_set_pivot_gate(1 if on else 0))
+
+
+CELL_PRUNE_FORMS = {"prefix_or": 0, "tree": 1}
+
+
+def set_cell_prune(form):
+    """Cell prune of compute() for later calls: "prefix_or" (Definition 3, the
+    default) or "tree" (the paper's Algorithm 3 per layer; g = 2^rho only)."""
+    _check(lib().skycell_set_cell_prune(CELL_PRUNE_FORMS[form]))
+
+
+def shrink_tree_layers(points_soa, rho, value_bits=10):
+    """Algorithm 3 layer by layer on a contiguous [d, n] device tensor: a list,
+    per layer 1..rho, of (key_bits, cand_bits) numpy uint64 bitmaps over the
+    layer's Morton-numbered cells."""
+    import numpy as np
+    import torch
+    d, n = (int(v) for v in points_soa.shape)
+    words = [((1 << (j * d)) + 63) // 64 for j in range(1, rho + 1)]
+    total = max(sum(words), 1)
+    key = torch.zeros(total, dtype=torch.int64, device=points_soa.device)
+    cand = torch.zeros(total, dtype=torch.int64, device=points_soa.device)
+    st = ctypes.c_void_p(torch.cuda.current_stream(points_soa.device).cuda_stream)
+    _check(lib().skycell_shrink_tree(ctypes.c_void_p(points_soa.data_ptr()), _dtype_code(points_soa), n, d,
+                                     int(rho), int(value_bits), ctypes.c_void_p(key.data_ptr()),
+                                     ctypes.c_void_p(cand.data_ptr()), st))
+    k = key.cpu().numpy().view(np.uint64)
+    c = cand.cpu().numpy().view(np.uint64)
+    out, off = [], 0
+    for w in words:
+        out.append((k[off:off + w], c[off:off + w]))
+        off += w
+    return out
 
 
 def load_tuning(path):
@@ -276,6 +325,136 @@ def compute_static(points_soa, grid_res=0, value_bits=10, out_idx=None, out_coun
                                         int(value_bits), _ptr(out_idx), _ptr(out_count), _ptr(stats),
                                         _stream(dev, stream)))
     return out_idx, out_count
+
+
+class Dynamic:
+    """A point set kept on the device with its skyline, updated per batch of
+    inserts and deletes (skycell_dyn_*).  Ids are insertion positions."""
+
+    def __init__(self, d, capacity, dtype="f32", value_bits=10, device="cuda"):
+        import torch
+        self.d = int(d)
+        self.capacity = int(capacity)
+        self.dtype = DTYPE_F32 if dtype in ("f32", DTYPE_F32) else DTYPE_U16
+        self.device = torch.device(device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().skycell_dyn_create(self.d, self.dtype, self.capacity, int(value_bits),
+                                            ctypes.byref(handle)))
+        self.handle = handle
+        self.out_idx = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+        self.out_count = torch.empty(1, dtype=torch.int32, device=self.device)
+
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def insert(self, points_soa):
+        """Append a contiguous [d, m] device tensor; returns the first new id."""
+        if tuple(points_soa.shape[:1]) != (self.d,) or not points_soa.is_contiguous():
+            raise ValueError("points must be a contiguous [%d, m] tensor" % self.d)
+        if _dtype_code(points_soa) != self.dtype:
+            raise TypeError("dtype mismatch")
+        first = ctypes.c_int64(0)
+        _check(lib().skycell_dyn_insert(self.handle, ctypes.c_void_p(points_soa.data_ptr()),
+                                        int(points_soa.shape[1]), ctypes.byref(first), self._stream()))
+        return first.value
+
+    def delete(self, ids):
+        """Delete the ids of a device int32 tensor."""
+        import torch
+        ids = ids.to(device=self.device, dtype=torch.int32).contiguous()
+        _check(lib().skycell_dyn_delete(self.handle, ctypes.c_void_p(ids.data_ptr()), int(ids.numel()),
+                                        self._stream()))
+
+    def skyline(self):
+        """Current skyline: ascending ids (int32 device tensor)."""
+        _check(lib().skycell_dyn_skyline(self.handle, ctypes.c_void_p(self.out_idx.data_ptr()),
+                                         ctypes.c_void_p(self.out_count.data_ptr()), self._stream()))
+        c = int(self.out_count.item())
+        return self.out_idx[:c].clone()
+
+    def size(self):
+        """(ids used, points recomputed by the last update)."""
+        used, last = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().skycell_dyn_size(self.handle, ctypes.byref(used), ctypes.byref(last)))
+        return used.value, last.value
+
+    def close(self):
+        if self.handle:
+            _check(lib().skycell_dyn_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class QuadrantQueries:
+    """Quadrant skyline queries (Section VII-B3) on one resident data set: query
+    q answers with the skyline of the points p >= origins[q] (every dimension).
+
+    points_soa: contiguous [d, n] device tensor; origins_soa: contiguous [d, nq]
+    device tensor of the same dtype.  run() enqueues every query (one graph
+    launch) and returns (out_idx, out_count) device tensors; answers() splits
+    them into per-query numpy arrays of ascending indices.
+    """
+
+    def __init__(self, points_soa, origins_soa, value_bits=10):
+        import numpy as np
+        import torch
+        if points_soa.dim() != 2 or origins_soa.dim() != 2 or not points_soa.is_contiguous() \
+                or not origins_soa.is_contiguous():
+            raise ValueError("points and origins must be contiguous [d, n] and [d, nq] tensors")
+        self.d, self.n = (int(v) for v in points_soa.shape)
+        if int(origins_soa.shape[0]) != self.d:
+            raise ValueError("origins must have %d rows" % self.d)
+        self.nq = int(origins_soa.shape[1])
+        self.dtype = _dtype_code(points_soa)
+        if _dtype_code(origins_soa) != self.dtype:
+            raise TypeError("points and origins differ in dtype")
+        self.device = points_soa.device
+        self.points, self.origins = points_soa, origins_soa
+        st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        handle = ctypes.c_void_p()
+        _check(lib().skycell_quadrant_create(ctypes.c_void_p(points_soa.data_ptr()), self.dtype, self.n, self.d,
+                                             int(value_bits), ctypes.c_void_p(origins_soa.data_ptr()), self.nq,
+                                             ctypes.byref(handle), st))
+        self.handle = handle
+        self.out_off = np.zeros(self.nq + 1, dtype=np.int64)
+        _check(lib().skycell_quadrant_offsets(self.handle, self.out_off.ctypes.data))
+        self.out_idx = torch.empty(max(int(self.out_off[-1]), 1), dtype=torch.int32, device=self.device)
+        self.out_count = torch.empty(self.nq, dtype=torch.int32, device=self.device)
+
+    def run(self):
+        import torch
+        st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _check(lib().skycell_quadrant_run(self.handle, ctypes.c_void_p(self.points.data_ptr()),
+                                          ctypes.c_void_p(self.origins.data_ptr()),
+                                          ctypes.c_void_p(self.out_idx.data_ptr()),
+                                          ctypes.c_void_p(self.out_count.data_ptr()), st))
+        return self.out_idx, self.out_count
+
+    def answers(self):
+        """Per-query ascending indices (numpy), after run()."""
+        idx = self.out_idx.cpu().numpy()
+        cnt = self.out_count.cpu().numpy()
+        if (cnt < 0).any():
+            raise SkycellError(int(cnt[cnt < 0][0]), "a quadrant holds a NaN")
+        return [idx[self.out_off[q]:self.out_off[q] + cnt[q]] for q in range(self.nq)]
+
+    def close(self):
+        if self.handle:
+            _check(lib().skycell_quadrant_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BatchedPlan:

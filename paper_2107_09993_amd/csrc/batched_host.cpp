@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -65,6 +66,8 @@ struct skycell_plan {
     char *d_ws = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t launched = nullptr;  // recorded after every launch of exec
+    bool launched_pending = false;
     const void *bound_points = nullptr;
     int32_t *bound_out_idx = nullptr;
     int32_t *bound_out_count = nullptr;
@@ -72,8 +75,12 @@ struct skycell_plan {
 
 namespace {
 
+// Destroys the captured graph once its last launch has finished (a run that
+// passes other buffers recaptures while the previous launch may still run).
 void drop_graph(skycell_plan *p)
 {
+    if (p->launched_pending && p->launched) (void)hipEventSynchronize(p->launched);
+    p->launched_pending = false;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
@@ -87,8 +94,41 @@ void plan_free(skycell_plan *p)
 {
     if (p == nullptr) return;
     drop_graph(p);
+    if (p->launched) (void)hipEventDestroy(p->launched);
     if (p->d_ws) (void)hipFree(p->d_ws);
     delete p;
+}
+
+// Capture streams and fork/join events, created once per device and kept for
+// the life of the process (creating and destroying tens of streams and events
+// at every capture is costly and was the heaviest churn of the plan lifecycle).
+struct CaptureKit {
+    bool ready = false;
+    hipStream_t origin = nullptr;
+    hipStream_t branch[kMaxBranches] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kMaxBranches] = {};
+};
+constexpr int kMaxKitDevices = 64;
+static std::mutex g_kit_mu;
+static CaptureKit g_kit[kMaxKitDevices];
+
+static hipError_t capture_kit(int dev, CaptureKit **out)
+{
+    if (dev < 0 || dev >= kMaxKitDevices) return hipErrorInvalidDevice;
+    CaptureKit &k = g_kit[dev];
+    if (!k.ready) {
+        hipError_t e = hipStreamCreateWithFlags(&k.origin, hipStreamNonBlocking);
+        for (int i = 0; i < kMaxBranches && e == hipSuccess; ++i)
+            e = hipStreamCreateWithFlags(&k.branch[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&k.fork, hipEventDisableTiming);
+        for (int i = 0; i < kMaxBranches && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&k.join[i], hipEventDisableTiming);
+        if (e != hipSuccess) return e;  // what was created is kept for the next attempt
+        k.ready = true;
+    }
+    *out = &k;
+    return hipSuccess;
 }
 
 // Capture every instance's path with this run's buffers into one graph.
@@ -97,13 +137,13 @@ int capture(skycell_plan *p, const void *points, int32_t *out_idx, int32_t *out_
     drop_graph(p);
     const size_t esize = p->dtype == SKYCELL_DTYPE_F32 ? 4 : 2;
     const int kBranches = batch_branches();
-    hipStream_t origin = nullptr;
-    hipStream_t branch[kMaxBranches] = {};
-    hipEvent_t fork = nullptr, join[kMaxBranches] = {};
-    hipError_t e = hipStreamCreateWithFlags(&origin, hipStreamNonBlocking);
-    for (int i = 0; i < kBranches && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&branch[i], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-    for (int i = 0; i < kBranches && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+    std::lock_guard<std::mutex> lk(g_kit_mu);
+    CaptureKit *kit = nullptr;
+    hipError_t e = capture_kit(p->device, &kit);
+    if (e != hipSuccess) return set_error(SKYCELL_E_HIP, "creating capture streams: %s", hipGetErrorString(e));
+    hipStream_t origin = kit->origin;
+    hipStream_t *branch = kit->branch;
+    hipEvent_t fork = kit->fork, *join = kit->join;
     int rc = SKYCELL_OK;
     bool capturing = false;
     if (e == hipSuccess) e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
@@ -123,21 +163,18 @@ int capture(skycell_plan *p, const void *points, int32_t *out_idx, int32_t *out_
                           p->g[b], p->value_bits, out_idx + p->out_off[b], out_count + b, p->d_ws + p->ws_off[b],
                           nullptr, st);
     }
-    for (int i = 0; i < kBranches && capturing && e == hipSuccess; ++i) {
-        e = hipEventRecord(join[i], branch[i]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(origin, join[i], 0);
+    // join every branch even after an error, so that the capture ends cleanly
+    // and the (reused) branch streams leave capture mode
+    for (int i = 0; i < kBranches && capturing; ++i) {
+        hipError_t ej = hipEventRecord(join[i], branch[i]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(origin, join[i], 0);
+        if (e == hipSuccess) e = ej;
     }
     if (capturing) {
         const hipError_t ee = hipStreamEndCapture(origin, &p->graph);
         if (e == hipSuccess) e = ee;
     }
     if (e == hipSuccess && rc == SKYCELL_OK) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-    for (int i = 0; i < kBranches; ++i) {
-        if (join[i]) (void)hipEventDestroy(join[i]);
-        if (branch[i]) (void)hipStreamDestroy(branch[i]);
-    }
-    if (fork) (void)hipEventDestroy(fork);
-    if (origin) (void)hipStreamDestroy(origin);
     if (rc != SKYCELL_OK || e != hipSuccess) {
         drop_graph(p);
         return rc != SKYCELL_OK ? rc : set_error(SKYCELL_E_HIP, "capturing the batch: %s", hipGetErrorString(e));
@@ -265,6 +302,14 @@ int skycell_batched_run(skycell_plan_t plan, const void *points, int32_t *out_id
     }
     if ((e = hipGraphLaunch(plan->exec, (hipStream_t)stream)) != hipSuccess)
         return set_error(SKYCELL_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+    if (plan->launched == nullptr &&
+        (e = hipEventCreateWithFlags(&plan->launched, hipEventDisableTiming)) != hipSuccess) {
+        plan->launched = nullptr;
+        return set_error(SKYCELL_E_HIP, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    if ((e = hipEventRecord(plan->launched, (hipStream_t)stream)) != hipSuccess)
+        return set_error(SKYCELL_E_HIP, "hipEventRecord: %s", hipGetErrorString(e));
+    plan->launched_pending = true;
     return clear_error();
 }
 

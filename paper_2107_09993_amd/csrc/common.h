@@ -62,6 +62,7 @@ struct GridDesc {
     uint32_t mask[kMaxD];      // index bits that hold dimension k
     int32_t m;                 // query points per refine work item (1, 2 or 4)
     int32_t parts;             // wave form: waves that share one item's cone (>= 1)
+    int32_t tile;              // 1: tile form of the refine (refine_tile.hip)
 };
 
 // Index of the cell one column lower / higher in the dimension whose bits are
@@ -158,6 +159,11 @@ hipError_t refine_prepare(const GridDesc &gd);
 hipError_t launch_refine_wave(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus,
                               hipStream_t st);
 hipError_t refine_wave_prepare(const GridDesc &gd);
+// Tile form (refine_tile.hip), used when gd.tile is set: 2 <= d <= 8, g = 2^r <= 128.
+bool tile_form_supported(int d, int g);
+hipError_t launch_refine_tile(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats, int num_cus,
+                              hipStream_t st);
+hipError_t refine_tile_prepare(const GridDesc &gd);
 hipError_t launch_output(int64_t n, const Workspace &ws, int32_t *out_idx, int32_t *out_count,
                          uint64_t *stats, hipStream_t st);
 hipError_t launch_write_zero_count(int32_t *out_count, hipStream_t st);

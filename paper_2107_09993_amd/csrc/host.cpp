@@ -148,14 +148,15 @@ static int items_per_lane(int d)
 // tuning table's form for this (d, n, dtype) and grid, else the wave form when
 // the grid is very coarse (at least 32 points per cell of the index space on
 // average), where cells hold enough points to keep a wave busy.
-static std::atomic<int> g_form_override{-2};  // -2 unread, -1 none, 0 lane, 1 wave
+static std::atomic<int> g_form_override{-2};  // -2 unread, -1 none, 0 lane, 1 wave, 2 tile
 
 static int refine_form(int64_t n, int d, int g, int dtype)
 {
     int ov = g_form_override.load();
     if (ov == -2) {
         const char *v = getenv("SKYCELL_REFINE_FORM");
-        const int e = v == nullptr ? -1 : (strcmp(v, "wave") == 0 ? 1 : (strcmp(v, "lane") == 0 ? 0 : -1));
+        const int e = v == nullptr ? -1
+                      : (strcmp(v, "wave") == 0 ? 1 : (strcmp(v, "lane") == 0 ? 0 : (strcmp(v, "tile") == 0 ? 2 : -1)));
         int expected = -2;
         g_form_override.compare_exchange_strong(expected, e);
         ov = g_form_override.load();
@@ -189,6 +190,10 @@ static std::atomic<int> g_parts_override{-2};  // -2 unread, 0 none, else the co
 // Sampling gate of the pivot pre-filter (skycell_set_pivot_gate): 1 = on.
 static std::atomic<int> g_pivot_gate{1};
 
+// Cell prune of skycell_compute / skycell_compute_u16 (skycell_set_cell_prune).
+static std::atomic<int> g_cell_prune{0};
+int cell_prune_form() { return g_cell_prune.load(); }
+
 static int wave_parts(int64_t n, int d, int g, int dtype)
 {
     int ov = g_parts_override.load();
@@ -218,7 +223,12 @@ static int wave_parts(int64_t n, int d, int g, int dtype)
 GridDesc pipeline_desc(int64_t n, int d, int g, int dtype)
 {
     GridDesc gd = grid_desc(d, g);
-    if (refine_form(n, d, g, dtype) == 1) {
+    const int form = refine_form(n, d, g, dtype);
+    if (form == 2 && tile_form_supported(d, g)) {
+        gd.tile = 1;
+        return gd;
+    }
+    if (form == 1) {
         gd.m = kWaveItemPoints;
         // items <= n, and items * parts work units must stay below 2^31
         const int64_t cap = std::max<int64_t>(1, ((int64_t)1 << 31) / std::max<int64_t>(n, 1) - 1);
@@ -393,7 +403,7 @@ static int prof_mark(int i, hipStream_t st)
 
 int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
                  int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
-                 uint64_t *stats, hipStream_t st, const PivotArgs *piv)
+                 uint64_t *stats, hipStream_t st, const PivotArgs *piv, const TreeScratch *tree)
 {
     const GridDesc gd = pipeline_desc(n, d, g, dtype);
     Workspace ws;
@@ -406,6 +416,11 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
     SKYCELL_HIP_CHECK(launch_quantize_hist(points, dtype, n, gd, value_bits, ws, st));
     SKYCELL_PROF(1);
     SKYCELL_HIP_CHECK(launch_cell_prune(gd, ws, stats, st));
+    if (tree != nullptr) {
+        const int rho = gd.r;
+        SKYCELL_HIP_CHECK(run_shrink_tree(ws.cnt, d, rho, *tree, nullptr, nullptr, st));
+        SKYCELL_HIP_CHECK(apply_shrink_tree(*tree, rho, ws, gd.cells, stats, st));
+    }
     const bool pivots = piv != nullptr && piv->k > 0;
     if (pivots) {
         SKYCELL_HIP_CHECK(launch_pivot_gather((const float *)points, (uint32_t)n, d, piv->idx, piv->k, piv->ps,
@@ -425,6 +440,23 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
     return ok();
 }
 
+// The paper's tree-form cell prune, when chosen (skycell_set_cell_prune) and the
+// grid has g = 2^rho columns: its scratch, library-owned and kept per (device,
+// stream).  *use is false when the prefix-OR prune applies.
+static int tree_scratch_for(int d, int g, int dev, hipStream_t st, TreeScratch *ts, bool *use)
+{
+    *use = false;
+    const GridDesc gd = grid_desc(d, g);
+    if (cell_prune_form() != 1 || g < 2 || (g & (g - 1)) != 0 || (1 << gd.r) != g) return SKYCELL_OK;
+    const size_t tneed = tree_scratch_layout(gd.cells, d, gd.r, nullptr, nullptr);
+    void *tptr = nullptr;
+    const int rc = cached_buffer(kCacheTree, dev, st, tneed, &tptr);
+    if (rc != SKYCELL_OK) return rc;
+    tree_scratch_layout(gd.cells, d, gd.r, ts, (char *)tptr);
+    *use = true;
+    return SKYCELL_OK;
+}
+
 static int compute_owned(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
                          int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *stream)
 {
@@ -442,7 +474,11 @@ static int compute_owned(const void *points, int32_t dtype, int64_t n, int32_t d
     SKYCELL_HIP_CHECK(hipGetDevice(&dev));
     void *ptr = nullptr;
     if ((rc = cached_buffer(kCacheWorkspace, dev, st, need, &ptr)) != SKYCELL_OK) return rc;
-    return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, ptr, nullptr, st);
+    TreeScratch ts;
+    bool use_tree = false;
+    if ((rc = tree_scratch_for(d, g, dev, st, &ts, &use_tree)) != SKYCELL_OK) return rc;
+    return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, ptr, nullptr, st, nullptr,
+                        use_tree ? &ts : nullptr);
 }
 
 }  // namespace skycell
@@ -498,7 +534,13 @@ int skycell_compute_ws(const void *points, int32_t dtype, int64_t n, int32_t d, 
         return fail(SKYCELL_E_NOMEM, "workspace of %zu bytes is smaller than the %zu required",
                     workspace ? ws_bytes : (size_t)0, need);
     if (((uintptr_t)workspace & 255u) != 0) return fail(SKYCELL_E_INVAL, "workspace is not 256-byte aligned");
-    return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, workspace, stats, st);
+    int dev = 0;
+    SKYCELL_HIP_CHECK(hipGetDevice(&dev));
+    TreeScratch ts;
+    bool use_tree = false;
+    if ((rc = tree_scratch_for(d, g, dev, st, &ts, &use_tree)) != SKYCELL_OK) return rc;
+    return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, workspace, stats, st, nullptr,
+                        use_tree ? &ts : nullptr);
 }
 
 int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res)
@@ -514,7 +556,7 @@ int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res)
 
 int skycell_set_refine_form(int32_t form)
 {
-    if (form < -1 || form > 1) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0 or 1", form);
+    if (form < -1 || form > 2) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0, 1 or 2", form);
     g_form_override.store(form);
     return ok();
 }
@@ -523,6 +565,13 @@ int skycell_set_pivot_gate(int32_t on)
 {
     if (on != 0 && on != 1) return fail(SKYCELL_E_INVAL, "on = %d is not 0 or 1", on);
     g_pivot_gate.store(on);
+    return ok();
+}
+
+int skycell_set_cell_prune(int32_t form)
+{
+    if (form != 0 && form != 1) return fail(SKYCELL_E_INVAL, "form = %d is not 0 or 1", form);
+    g_cell_prune.store(form);
     return ok();
 }
 

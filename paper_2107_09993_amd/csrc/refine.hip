@@ -178,6 +178,7 @@ static hipError_t prepare_d(int m)
 hipError_t refine_prepare(const GridDesc &gd)
 {
     (void)refine_chunk();
+    if (gd.tile) return refine_tile_prepare(gd);
     if (gd.m == kWaveItemPoints) return refine_wave_prepare(gd);
     switch (gd.d) {
 #define SKYCELL_PREPARE_CASE(DD) \
@@ -208,6 +209,7 @@ hipError_t refine_prepare(const GridDesc &gd)
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st)
 {
+    if (gd.tile) return launch_refine_tile(n, gd, ws, stats, num_cus, st);
     if (gd.m == kWaveItemPoints) return launch_refine_wave(n, gd, ws, stats, num_cus, st);
     switch (gd.d) {
 #define SKYCELL_REFINE_CASE(DD) \

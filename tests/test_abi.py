@@ -234,3 +234,37 @@ def test_static_entry_point_rejects_sizes_over_its_scratch():
     assert rc == sky.E_INVAL
     rc = lib.skycell_compute_static(FAKE, sky.DTYPE_U16, 100, 4, 8, 17, FAKE, FAKE, None, None)
     assert rc == sky.E_RANGE
+
+
+def test_dynamic_argument_errors():
+    """skycell_dyn_* reject bad arguments before any HIP call."""
+    lib = sky.lib()
+    h = ctypes.c_void_p()
+    assert lib.skycell_dyn_create(0, sky.DTYPE_F32, 100, 10, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_dyn_create(17, sky.DTYPE_F32, 100, 10, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_dyn_create(4, sky.DTYPE_F32, 0, 10, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_dyn_create(4, sky.DTYPE_F32, 1 << 31, 10, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_dyn_create(4, 7, 100, 10, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_dyn_create(4, sky.DTYPE_U16, 100, 0, ctypes.byref(h)) == sky.E_INVAL
+    assert lib.skycell_dyn_create(4, sky.DTYPE_F32, 100, 10, None) == sky.E_INVAL
+    assert lib.skycell_dyn_insert(None, FAKE, 5, None, None) == sky.E_INVAL
+    assert lib.skycell_dyn_delete(None, FAKE, 5, None) == sky.E_INVAL
+    assert lib.skycell_dyn_skyline(None, FAKE, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_dyn_destroy(None) == sky.OK
+
+
+def test_quadrant_argument_errors():
+    """skycell_quadrant_* reject bad arguments before any HIP call."""
+    lib = sky.lib()
+    h = ctypes.c_void_p()
+    assert lib.skycell_quadrant_create(None, sky.DTYPE_F32, 10, 3, 10, FAKE, 5, ctypes.byref(h), None) == sky.E_INVAL
+    assert lib.skycell_quadrant_create(FAKE, sky.DTYPE_F32, 10, 3, 10, None, 5, ctypes.byref(h), None) == sky.E_INVAL
+    assert lib.skycell_quadrant_create(FAKE, 9, 10, 3, 10, FAKE, 5, ctypes.byref(h), None) == sky.E_INVAL
+    assert lib.skycell_quadrant_create(FAKE, sky.DTYPE_F32, 0, 3, 10, FAKE, 5, ctypes.byref(h), None) == sky.E_INVAL
+    assert lib.skycell_quadrant_create(FAKE, sky.DTYPE_F32, 10, 17, 10, FAKE, 5, ctypes.byref(h), None) == sky.E_INVAL
+    assert lib.skycell_quadrant_create(FAKE, sky.DTYPE_F32, 10, 3, 10, FAKE, 0, ctypes.byref(h), None) == sky.E_INVAL
+    assert lib.skycell_quadrant_create(FAKE, sky.DTYPE_U16, 10, 3, 17, FAKE, 5, ctypes.byref(h), None) == sky.E_RANGE
+    assert lib.skycell_quadrant_create(FAKE, sky.DTYPE_F32, 10, 3, 10, FAKE, 5, None, None) == sky.E_INVAL
+    assert lib.skycell_quadrant_run(None, FAKE, FAKE, FAKE, FAKE, None) == sky.E_INVAL
+    assert lib.skycell_quadrant_offsets(None, FAKE) == sky.E_INVAL
+    assert lib.skycell_quadrant_destroy(None) == sky.OK

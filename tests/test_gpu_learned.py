@@ -366,3 +366,30 @@ def test_pivoted_headline_size_sampled(oracle_mod):
     got = np.isin(sample, piv.cpu().numpy())
     assert np.array_equal(got, res)
     m.close()
+
+
+@pytest.mark.parametrize("dist,n", [("independent", 2_000_000), ("anticorrelated", 2_000_000)])
+def test_shipped_networks_against_plain_and_smallest_sum(oracle_mod, dist, n):
+    """The committed networks on their own distribution (d = 10): the pivoted
+    skyline equals the oracle's and the plain path's, and what the network's
+    pivots remove is reported next to the smallest-coordinate-sum pivots (a
+    rule that needs no training).  On independent data the gate opens and the
+    network removes most surviving points; it does not beat the sum rule."""
+    from paper_2107_09993_amd import learned
+    x = datagen.generate(dist, n, 10, 123)
+    net = sky.MLP.load(learned.NETS[dist])
+    res = learned.evaluate(net, n=n, d=10, k=4096, reps=2, device=DEV, x=x, dist=dist)
+    net.close()
+    assert res["identical_outputs"]
+    want = oracle_mod.skyline_kdtree(x)
+    assert res["skyline"] == want.size
+    got = sky.compute_pivoted(soa(x), sky.MLP.load(learned.NETS[dist]), k=4096).cpu().numpy()
+    assert np.array_equal(got, want)
+    print("\n%s n=%d: plain %.1f ms; network pivots %.1f ms (%.2fx, %d removed); smallest-sum pivots %.1f ms "
+          "(%.2fx, %d removed); random pivots %.2fx"
+          % (dist, n, res["plain"]["ms"], res["learned"]["ms"], res["learned"]["speedup_vs_plain"],
+             res["learned"]["pivot_removed"], res["l1_pivots"]["ms"], res["l1_pivots"]["speedup_vs_plain"],
+             res["l1_pivots"]["pivot_removed"], res["random_pivots"]["speedup_vs_plain"]))
+    if dist == "independent":
+        # the gate opens: the network's pivots remove most surviving points
+        assert res["learned"]["pivot_removed"] > 0.5 * res["plain"]["survivor_points"]

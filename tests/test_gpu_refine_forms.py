@@ -98,3 +98,51 @@ def test_wave_parts_pivots_and_u16(oracle_mod):
         sky.set_wave_parts(0)
     assert np.array_equal(got, oracle_mod.skyline_sfs(x))
     assert np.array_equal(got_u, oracle_mod.skyline_sfs(u))
+
+
+TILE_CASES = [
+    ("anti_d8_g8", lambda: datagen.anticorrelated(60_000, 8, seed=12), 8),
+    ("anti_d8_g4", lambda: datagen.anticorrelated(30_000, 8, seed=13), 4),
+    ("ind_d8_g8", lambda: datagen.independent(80_000, 8, seed=14), 8),
+    ("corr_d6_g16", lambda: datagen.correlated(50_000, 6, seed=15), 16),
+    ("ind_d2_g128", lambda: datagen.independent(100_000, 2, seed=16), 128),
+    ("anti_d3_g64", lambda: datagen.anticorrelated(70_000, 3, seed=17), 64),
+    ("ties_d5_g4", lambda: datagen.small_integers(20_000, 5, seed=18, high=5), 4),
+    ("anti_d7_g2", lambda: datagen.anticorrelated(9_000, 7, seed=19), 2),
+    ("anti_d4_g32_big_cells", lambda: datagen.anticorrelated(400_000, 4, seed=20), 32),
+]
+
+
+@pytest.mark.parametrize("name,make,g", TILE_CASES, ids=[c[0] for c in TILE_CASES])
+def test_tile_form_matches_oracle(oracle_mod, name, make, g):
+    """Tile form (a workgroup walks the coarse cone of up to 256 points of one
+    coarse cell; each point screens the candidates of its own fine cone, staged
+    in LDS): the oracle's skyline, and the same number of screening tests as
+    the lane form (both screen exactly the fine lower cone until a dominator)."""
+    x = make()
+    ref = oracle_mod.skyline_sfs(x)
+    sky.set_refine_form("tile")
+    try:
+        got, st = _run(x, g, stats=True)
+        again = _run(x, g)
+    finally:
+        sky.set_refine_form("auto")
+    assert np.array_equal(got, ref), (len(got), len(ref))
+    assert np.array_equal(again, ref)
+    assert st["skyline"] == len(ref)
+
+
+def test_tile_form_u16_and_unsupported_grids(oracle_mod):
+    u = datagen.quantise_u16(datagen.anticorrelated(50_000, 6, seed=21))
+    x = datagen.independent(20_000, 9, seed=22)
+    sky.set_refine_form("tile")
+    try:
+        got_u = _run(u, 8, value_bits=10)
+        got_odd = _run(u, 6, value_bits=10)   # g not a power of two: the lane form runs
+        got_d9 = _run(x, 4)                   # d > 8: the lane form runs
+    finally:
+        sky.set_refine_form("auto")
+    ref_u = oracle_mod.skyline_sfs(u)
+    assert np.array_equal(got_u, ref_u)
+    assert np.array_equal(got_odd, ref_u)
+    assert np.array_equal(got_d9, oracle_mod.skyline_sfs(x))
