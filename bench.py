@@ -247,13 +247,16 @@ def cpu_baseline(x_host, sample):
 def phase_bytes(n, d, cells, st):
     """Bytes each streaming phase must move at least with this data layout
     (reads + writes, every array touched once), for the per-phase bandwidth."""
+    r = max(1, (cells.bit_length() - 1) // d)
     fw = 8 * ((d + 7) // 8)
     surv = st["survivor_points"]
     return {
         # zero the counts; read the coordinates, write cell and rank per point
         "quantize_hist": 4 * cells + n * (4 * d + 8),
-        # counts -> occupancy byte, d prefix-OR passes over it, records
-        "cell_prune": cells * (4 + 1 + 2 * d + 4 + 1 + 8),
+        # counts -> occupancy bits; prefix-OR steps over the bitmap (one pass
+        # inside words, one per column bit above: read two words, write one);
+        # counts and records
+        "cell_prune": cells * (4 + 8) + (cells // 8) * (1 + 2 + max(0, r * d - 6) * 3 // 2),
         # reduce and emit passes over (record, count), start words, work items
         "cell_scan": cells * (12 + 12 + 4) + st["items"] * 8,
         # coordinates, cell, rank, record per point; keys, screening words,

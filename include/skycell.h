@@ -254,7 +254,8 @@ int skycell_shrink_tree(const void *points, int32_t dtype, int64_t n, int32_t d,
  *                                c[k] at index bit b*d + k, r = ceil(log2 g) bits
  *   1 rank     uint32 [n]        position of the point among the points of its cell
  *   2 cnt      uint32 [cells]    histogram, cells = 2^(r*d)
- *   3 lc       uint8  [cells]    lower closure of the occupancy
+ *   3 lc       uint64 [cells/64+1] lower closure of the occupancy, one bit per cell
+ *                                (bit x of word x/64: some non-empty cell is <= x)
  *   4 rec      uint64 [cells+1]  per-cell record: bits 0-31 first sorted position,
  *                                32-46 point count (saturated at 0x7FFF), 47-62 mask
  *                                (bit k: the cone one column lower in dimension k

@@ -62,6 +62,7 @@ def lib():
     L.skycell_set_wave_parts.argtypes = [i32]
     L.skycell_set_pivot_gate.argtypes = [i32]
     L.skycell_set_cell_prune.argtypes = [i32]
+    L.skycell_compute_layered.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, p]
     L.skycell_shrink_tree.argtypes = [p, i32, i64, i32, i32, i32, p, p, p]
     L.skycell_workspace_layout.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz), i32]
     L.skycell_profile_enable.argtypes = [i32]
@@ -102,7 +103,7 @@ def lib():
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
                  "skycell_compute_ws", "skycell_compute_static", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
                  "skycell_set_wave_parts", "skycell_set_pivot_gate", "skycell_set_cell_prune",
-                 "skycell_shrink_tree",
+                 "skycell_shrink_tree", "skycell_compute_layered",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
                  "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
                  "skycell_plan_destroy", "skycell_mlp_num_params", "skycell_mlp_create",
@@ -303,6 +304,32 @@ def compute(points, grid_res=0, layout="nd", value_bits=10, return_stats=False):
     out = sk.result().clone()
     if return_stats:
         return out, sk.stats_dict()
+    return out
+
+
+def compute_layered(points_soa, rho, value_bits=10, return_stats=False):
+    """Exact skyline of a contiguous [d, n] tensor with two grid layers: the
+    dense base grid of 2^(rho-1) columns and an exact Definition 3 prune at
+    2^rho columns kept as occupancy bits (skycell_compute_layered)."""
+    import torch
+    if not points_soa.is_contiguous() or points_soa.dim() != 2:
+        raise ValueError("points must be a contiguous [d, n] tensor")
+    d, n = (int(v) for v in points_soa.shape)
+    dev = points_soa.device
+    out_idx = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    out_count = torch.empty(1, dtype=torch.int32, device=dev)
+    stats = torch.zeros(NUM_STATS, dtype=torch.int64, device=dev) if return_stats else None
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(lib().skycell_compute_layered(ctypes.c_void_p(points_soa.data_ptr()), _dtype_code(points_soa), n, d,
+                                         int(rho), int(value_bits), ctypes.c_void_p(out_idx.data_ptr()),
+                                         ctypes.c_void_p(out_count.data_ptr()),
+                                         ctypes.c_void_p(stats.data_ptr()) if stats is not None else None, st))
+    c = int(out_count.item())
+    if c < 0:
+        raise SkycellError(c, "device reported %s" % ("NaN in input" if c == E_NAN else "error"))
+    out = out_idx[:c].clone()
+    if return_stats:
+        return out, dict(zip(STAT_NAMES, (int(v) for v in stats.cpu().tolist())))
     return out
 
 

@@ -48,43 +48,50 @@ __device__ __forceinline__ uint32_t point_cell(const T *__restrict__ pts, uint32
     return cell;
 }
 
-// Inclusive prefix-OR of the lower-closure flags along one line of cells that
-// differ only in the dimension whose index bits are `m` (line t of all_bits >> r).
-__device__ __forceinline__ void lc_prefix_line(uint8_t *__restrict__ lc, uint32_t t, uint32_t m,
-                                               uint32_t all_bits, uint32_t g)
+// Lower closure as a bitmap: bit x of lcb[x >> 6] is 1 iff some non-empty cell
+// is <= x in every dimension.
+__device__ __forceinline__ bool lc_bit(const uint64_t *__restrict__ lcb, uint32_t x)
 {
-    uint32_t x = deposit_bits(t, all_bits & ~m);
-    uint8_t v = 0;
-    // eight columns at a time: all loads of a chunk are issued before its stores
-    constexpr uint32_t kChunk = 8;
-    for (uint32_t j0 = 0; j0 < g; j0 += kChunk) {
-        const uint32_t len = g - j0 < kChunk ? g - j0 : kChunk;
-        uint32_t xs[kChunk];
-        uint8_t f[kChunk];
-#pragma unroll
-        for (uint32_t u = 0; u < kChunk; ++u) {
-            xs[u] = x;
-            f[u] = u < len ? lc[x] : (uint8_t)0;
-            if (u + 1 < len) x = morton_inc(x, m);
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < kChunk; ++u) {
-            if (u < len) {
-                v |= f[u];
-                lc[xs[u]] = v;
-            }
-        }
-        if (j0 + kChunk < g) x = morton_inc(x, m);
-    }
+    return ((lcb[x >> 6] >> (x & 63u)) & 1ull) != 0ull;
+}
+
+// Cells i in [0, 64) of one bitmap word whose index bit q is set.
+__host__ __device__ __forceinline__ uint64_t bit_set_pattern(int q)
+{
+    return q == 0 ? 0xAAAAAAAAAAAAAAAAull
+           : q == 1 ? 0xCCCCCCCCCCCCCCCCull
+           : q == 2 ? 0xF0F0F0F0F0F0F0F0ull
+           : q == 3 ? 0xFF00FF00FF00FF00ull
+           : q == 4 ? 0xFFFF0000FFFF0000ull
+                    : 0xFFFFFFFF00000000ull;
+}
+
+// One step of the prefix-OR along a dimension k, at column bit level b: every
+// cell whose column k has bit b set takes the OR of the cell with that bit
+// cleared and the lower bits of column k all set.  Applied for b = 0, 1, ...
+// this makes x the OR over every cell that differs from x only in a smaller or
+// equal column k.  `p` is the index bit of (k, b), `lowk` the index bits of
+// column k below b.  Within a word (index bits 0..5) it is a shift of the
+// word; above, a word ORs in another word.
+__host__ __device__ __forceinline__ uint64_t lc_step_word(uint64_t w, uint64_t src, int p, uint32_t lowk)
+{
+    const uint32_t lowlo = lowk & 63u;
+    uint64_t m = p < 6 ? (w & ~bit_set_pattern(p)) : src;
+    for (int q = 0; q < 6; ++q)
+        if (lowlo & (1u << q)) m &= bit_set_pattern(q);
+    if (p < 6) m <<= (1u << p);
+    for (int q = 0; q < 6; ++q)
+        if (lowlo & (1u << q)) m |= (m & bit_set_pattern(q)) >> (1u << q);
+    return w | m;
 }
 
 // Cell record without its start (see common.h):
-//   dominated(x)  iff  every column of x is >= 1 and lc[x - (1,...,1)] = 1,
+//   dominated(x)  iff  every column of x is >= 1 and lc(x - (1,...,1)) = 1,
 //   i.e. a non-empty cell has a smaller column in every dimension (Definition 3);
-//   mask bit k    iff  column k of x is >= 1 and lc[x - e_k] = 1, i.e. the cone
+//   mask bit k    iff  column k of x is >= 1 and lc(x - e_k) = 1, i.e. the cone
 //                      below x - e_k still holds a non-empty cell.
 __device__ __forceinline__ uint64_t cell_record(const GridDesc &gd, const uint32_t *__restrict__ cnt,
-                                                const uint8_t *__restrict__ lc, uint32_t x,
+                                                const uint64_t *__restrict__ lcb, uint32_t x,
                                                 bool &occ, bool &surv)
 {
     uint32_t nbr = 0u, diag = x;
@@ -94,13 +101,13 @@ __device__ __forceinline__ uint64_t cell_record(const GridDesc &gd, const uint32
         if ((x & m) == 0u) {
             all_pos = false;
         } else {
-            if (lc[morton_dec(x, m)]) nbr |= 1u << k;
+            if (lc_bit(lcb, morton_dec(x, m))) nbr |= 1u << k;
             diag = morton_dec(diag, m);
         }
     }
     const uint32_t c = cnt[x];
     occ = c != 0u;
-    surv = occ && !(all_pos && lc[diag]);
+    surv = occ && !(all_pos && lc_bit(lcb, diag));
     const uint64_t cs = surv ? (c < kRecCountSat ? c : kRecCountSat) : 0u;
     return ((uint64_t)(surv ? 1u : 0u) << 63) | ((uint64_t)nbr << 47) | (cs << 32);
 }

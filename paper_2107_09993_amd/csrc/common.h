@@ -92,7 +92,7 @@ struct Workspace {
     uint32_t *cell_of;    // [n]     cell of each input point
     uint32_t *rank;       // [n]     position of each point among the points of its cell
     uint32_t *cnt;        // [cells] points per cell
-    uint8_t *lc;          // [cells] lower closure: some non-empty cell <= this one
+    uint64_t *lc;         // [cells / 64 + 1] lower closure bitmap: some non-empty cell <= this one
     uint64_t *rec;        // [cells + 1] cell records (see above)
     uint32_t *keys;       // [n * d] order-preserving keys of surviving points, AoS, sorted by cell
     uint64_t *fkeys;      // [n * fine_words(d)] packed screening columns, same order

@@ -106,28 +106,52 @@ hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const Gri
 }
 
 // ------------------------------------------------------------------ K3
-// lc[x] = 1 iff some non-empty cell y has y <= x in every dimension.  Built as
-// the occupancy followed by an inclusive prefix-OR along each dimension.
+// Lower closure bitmap: bit x is 1 iff some non-empty cell y has y <= x in
+// every dimension.  Built as the occupancy bits (one wave ballot per 64 cells)
+// followed by an inclusive prefix-OR along each dimension, one column bit
+// level at a time (lc_step_word): the steps inside a word all run in one
+// pass; each step above runs as one pass over the 2 MB (2^24 cells) bitmap.
 __global__ __launch_bounds__(kThreads) void k_lc_init(const uint32_t *__restrict__ cnt,
-                                                      uint8_t *__restrict__ lc, uint32_t cells)
+                                                      uint64_t *__restrict__ lcb, uint32_t cells)
 {
     const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
-    if (x < cells) lc[x] = cnt[x] != 0u ? 1 : 0;
+    const uint64_t b = __ballot(x < cells && cnt[x] != 0u);
+    if (__lane_id() == 0 && x < cells) lcb[x >> 6] = b;
 }
 
-// One thread per line of cells that differ only in the dimension whose index
-// bits are `m`; the line is walked from column 0 up to column g-1.
-__global__ __launch_bounds__(kThreads) void k_lc_prefix(uint8_t *__restrict__ lc, uint32_t lines,
-                                                        uint32_t m, uint32_t all_bits, uint32_t g)
+// Every step whose index bit is inside a word (p < 6), for every dimension in
+// order of its column bits.
+__global__ __launch_bounds__(kThreads) void k_lc_inword(uint64_t *__restrict__ lcb, uint32_t words, GridDesc gd)
 {
-    const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
-    if (t < lines) lc_prefix_line(lc, t, m, all_bits, g);
+    const uint32_t wi = blockIdx.x * kThreads + threadIdx.x;
+    if (wi >= words) return;
+    uint64_t w = lcb[wi];
+    for (int k = 0; k < gd.d; ++k) {
+        uint32_t lowk = 0u;
+        for (int b = 0; b < gd.r; ++b) {
+            const int p = b * gd.d + k;
+            if (p >= 6) break;
+            w = lc_step_word(w, 0ull, p, lowk);
+            lowk |= 1u << p;
+        }
+    }
+    lcb[wi] = w;
+}
+
+// One step with index bit p >= 6: word W with bit p - 6 set ORs in word
+// (W without that bit) | (lowk >> 6), spread over the low index bits of lowk.
+__global__ __launch_bounds__(kThreads) void k_lc_step(uint64_t *__restrict__ lcb, uint32_t words, int p, uint32_t lowk)
+{
+    const uint32_t wi = blockIdx.x * kThreads + threadIdx.x;
+    if (wi >= words || ((wi >> (p - 6)) & 1u) == 0u) return;
+    const uint32_t si = (wi & ~(1u << (p - 6))) | (lowk >> 6);
+    lcb[wi] = lc_step_word(lcb[wi], lcb[si], p, lowk);
 }
 
 // Per cell: the high half of the cell record (see cellops.h); the scan fills
 // in the low half (first sorted position).
 __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32_t *__restrict__ cnt,
-                                                       const uint8_t *__restrict__ lc,
+                                                       const uint64_t *__restrict__ lc,
                                                        uint64_t *__restrict__ rec,
                                                        uint64_t *__restrict__ survbits,
                                                        uint64_t *__restrict__ stats)
@@ -153,11 +177,17 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *
 {
     hipLaunchKernelGGL(k_lc_init, grid_for(gd.cells), dim3(kThreads), 0, st, ws.cnt, ws.lc, gd.cells);
     if (gd.g > 1) {
-        const uint32_t lines = gd.cells >> gd.r;
-        const uint32_t all_bits = gd.cells - 1u;
-        for (int k = 0; k < gd.d; ++k)
-            hipLaunchKernelGGL(k_lc_prefix, grid_for(lines), dim3(kThreads), 0, st, ws.lc, lines,
-                               gd.mask[k], all_bits, (uint32_t)gd.g);
+        const uint32_t words = (gd.cells + 63u) / 64u;
+        hipLaunchKernelGGL(k_lc_inword, grid_for(words), dim3(kThreads), 0, st, ws.lc, words, gd);
+        for (int k = 0; k < gd.d; ++k) {
+            uint32_t lowk = 0u;
+            for (int b = 0; b < gd.r; ++b) {
+                const int p = b * gd.d + k;
+                if (p >= 6)
+                    hipLaunchKernelGGL(k_lc_step, grid_for(words), dim3(kThreads), 0, st, ws.lc, words, p, lowk);
+                lowk |= 1u << p;
+            }
+        }
     }
     hipLaunchKernelGGL(k_cell_rec, grid_for(gd.cells), dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
                        ws.rec, ws.survbits, stats);

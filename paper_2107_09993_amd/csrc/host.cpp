@@ -268,7 +268,7 @@ size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *b
     w.cell_of = (uint32_t *)take(4 * nn);
     w.rank = (uint32_t *)take(4 * nn);
     w.cnt = (uint32_t *)take(4 * (size_t)cells);
-    w.lc = (uint8_t *)take((size_t)cells);
+    w.lc = (uint64_t *)take(8 * ((size_t)cells / 64 + 1));
     w.rec = (uint64_t *)take(8 * ((size_t)cells + 1));
     w.keys = (uint32_t *)take(4 * nn * (size_t)d);
     w.fkeys = (uint64_t *)take(8 * nn * (size_t)fine_words(d));

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include "cellops.h"
 #include "common.h"
 #include "scan.h"
 #include "../../include/skycell.h"
@@ -55,7 +56,7 @@ __device__ __forceinline__ uint64_t submask_word(uint32_t f)
 // lower closure.
 template <int D>
 __global__ __launch_bounds__(256) void k_tile_coarse(GridDesc gd, const uint64_t *__restrict__ rec,
-                                                     const uint8_t *__restrict__ lc, uint32_t ccells,
+                                                     const uint64_t *__restrict__ lc, uint32_t ccells,
                                                      uint2 *__restrict__ crun, uint32_t *__restrict__ cnbr)
 {
     const uint32_t y = blockIdx.x * 256 + threadIdx.x;
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(256) void k_tile_coarse(GridDesc gd, const uint64_t
         const uint32_t cm = gd.mask[k] >> D;
         if (y & cm) {
             const uint32_t yk = morton_dec(y, cm);
-            if (lc[((size_t)yk << D) | kSub]) nbr |= 1u << k;
+            if (lc_bit(lc, (yk << D) | kSub)) nbr |= 1u << k;
         }
     }
     crun[y] = make_uint2(start, end);
@@ -314,7 +315,7 @@ static hipError_t launch_tile_d(int64_t n, const GridDesc &gd, const Workspace &
     uint2 *crun = reinterpret_cast<uint2 *>(ws.cnt);
     uint32_t *cnbr = reinterpret_cast<uint32_t *>(crun + ccells + 1);
     hipLaunchKernelGGL(k_tile_coarse<D>, dim3((ccells + 255) / 256), dim3(256), 0, st, gd, (const uint64_t *)ws.rec,
-                       (const uint8_t *)ws.lc, ccells, crun, cnbr);
+                       (const uint64_t *)ws.lc, ccells, crun, cnbr);
     UnitLoader ld{crun};
     UnitEmitter em{ws.items};
     hipError_t e = enqueue_scan<uint32_t>(ld, em, ccells, ws.block_sums, st);

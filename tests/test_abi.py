@@ -268,3 +268,12 @@ def test_quadrant_argument_errors():
     assert lib.skycell_quadrant_run(None, FAKE, FAKE, FAKE, FAKE, None) == sky.E_INVAL
     assert lib.skycell_quadrant_offsets(None, FAKE) == sky.E_INVAL
     assert lib.skycell_quadrant_destroy(None) == sky.OK
+
+
+def test_layered_argument_errors():
+    lib = sky.lib()
+    assert lib.skycell_compute_layered(FAKE, sky.DTYPE_F32, 10, 1, 3, 10, FAKE, FAKE, None, None) == sky.E_INVAL
+    assert lib.skycell_compute_layered(FAKE, sky.DTYPE_F32, 10, 9, 3, 10, FAKE, FAKE, None, None) == sky.E_INVAL
+    assert lib.skycell_compute_layered(FAKE, sky.DTYPE_F32, 10, 8, 5, 10, FAKE, FAKE, None, None) == sky.E_RANGE
+    assert lib.skycell_compute_layered(FAKE, sky.DTYPE_F32, 10, 8, 1, 10, FAKE, FAKE, None, None) == sky.E_RANGE
+    assert lib.skycell_compute_layered(None, sky.DTYPE_F32, 10, 8, 4, 10, FAKE, FAKE, None, None) == sky.E_INVAL
