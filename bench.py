@@ -70,7 +70,7 @@ def parse():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("refine.hip", "refine_core.h", "common.h"):
+    for f in ("refine.hip", "refine_core.h", "refine_mc.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2107_09993_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -250,6 +250,9 @@ def phase_bytes(n, d, cells, st):
     r = max(1, (cells.bit_length() - 1) // d)
     fw = 8 * ((d + 7) // 8)
     surv = st["survivor_points"]
+    # walk records are built for the lane form only (its items hold at most two
+    # points, the wave form's up to 63)
+    walk_records = d <= 8 and 2 * st["items"] >= surv
     return {
         # zero the counts; read the coordinates, write cell and rank per point
         "quantize_hist": 4 * cells + n * (4 * d + 8),
@@ -260,8 +263,11 @@ def phase_bytes(n, d, cells, st):
         # reduce and emit passes over (record, count), start words, work items
         "cell_scan": cells * (12 + 12 + 4) + st["items"] * 8,
         # coordinates, cell, rank, record per point; keys, screening words,
-        # original index of surviving points; flag of every point
-        "scatter": n * (4 * d + 16 + 1) + surv * (4 * d + fw + 4),
+        # original index of surviving points; flag of every point; then for
+        # d <= 8 the walk records (read the cell records and the screening
+        # words, write one word per cell)
+        "scatter": n * (4 * d + 16 + 1) + surv * (4 * d + fw + 4)
+                   + (cells * 16 + surv * fw if walk_records else 0),
         # flags of every point, indices of the skyline points
         "output": n + 4 * st["skyline"],
     }
@@ -337,16 +343,18 @@ def main():
     achieved = ops / (refine_ms * 1e-3)
     workload = "%s n=%d d=%d seed=%d" % (a.dist, a.n, a.d, a.seed)
     # bytes the refine must move at least: keys, screening words and original
-    # index of every surviving point, the cell records, the work items, flags
+    # index of every surviving point, the cell records (and for d <= 8 the
+    # walk records), the work items, flags
     cells = (1 << (max(1, (g - 1).bit_length()) * a.d)) if g > 1 else 1
     algo_bytes = (st["survivor_points"] * (4 * a.d + 8 * ((a.d + 7) // 8) + 4) + (cells + 1) * 8
-                  + st["items"] * 8 + a.n)
+                  + (cells * 8 if a.d <= 8 else 0) + st["items"] * 8 + a.n)
     pbytes = phase_bytes(a.n, a.d, cells, st)
     phase_hbm = {k: {"algorithmic_bytes": b, "gbs": b / (phases[k] * 1e-3) / 1e9,
                      "frac_of_hbm_peak": b / (phases[k] * 1e-3) / PEAK_HBM}
                  for k, b in pbytes.items() if phases.get(k, 0.0) > 0.0}
     traffic = measured_traffic("k_refine", workload)
-    roof = {"kernel": "k_refine<%d>" % a.d, "bound": "alu", "achieved": achieved / 1e12,
+    kname = "k_refine<%d, 2, %s>" % (a.d, "true" if a.d <= 8 else "false")
+    roof = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12,
             "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_ALU_OPS,
             "traffic": traffic,
             # measured bytes per launch / launch time (rocprofv3 FETCH_SIZE + WRITE_SIZE)

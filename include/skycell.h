@@ -187,10 +187,14 @@ int skycell_load_tuning(const char *path);
  * Refine form for all later calls in the process: -1 = chosen per call (the
  * tuning table's form for the call's d, n and grid, else the wave form when
  * the grid has at most n/32 cells), 0 = lane form (one lane walks the lower
- * cone of a few points of one cell), 1 = wave form (one wave walks the cone of
- * up to 63 points of one cell and tests every candidate against all of them).
- * The result never depends on the form; this is for tests and tuning sweeps.
- * SKYCELL_REFINE_FORM=lane|wave in the environment sets it at the first call.
+ * cone of a few points of one cell; for d <= 8 it passes over every cell whose
+ * per-dimension minimum corner rules out its points as dominators), 1 = wave
+ * form (one wave walks the cone of up to 63 points of one cell and tests every
+ * candidate against all of them), 2 = tile form (grids of 2..128 columns, a
+ * power of two, and d = 2..8; else as -1), 3 = lane form without the minimum
+ * corners (kept for comparisons).  The result never depends on the form; this
+ * is for tests and tuning sweeps.  SKYCELL_REFINE_FORM=lane|wave|tile|plain in
+ * the environment sets it at the first call.
  */
 int skycell_set_refine_form(int32_t form);
 
@@ -264,8 +268,10 @@ int skycell_shrink_tree(const void *points, int32_t dtype, int64_t n, int32_t d,
  *   6 fkeys    uint64 [n*ceil(d/8)]  7-bit screening columns, one byte per dimension
  *   7 sidx     int32  [n]        original index of each sorted point
  *   8 items, 9 flag, 10 block sums, 11 counters, 12 total size (past the
- *   counters: a bitmap of surviving cells and, for n >= 2^20, the staging
- *   rows of the two-pass scatter).
+ *   counters: a bitmap of surviving cells, for n >= 2^20 the staging rows of
+ *   the two-pass scatter, and for d <= 8 one walk-record word per cell: the
+ *   lower-neighbour mask and the cell's minimum screening column per
+ *   dimension, read by the lane form of the refine).
  * count must be >= 13.  Returns SKYCELL_OK or an argument error.
  */
 int skycell_workspace_layout(int64_t n, int32_t d, int32_t grid_res, int32_t dtype,

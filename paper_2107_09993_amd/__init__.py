@@ -165,11 +165,12 @@ def workspace_layout(n, d, grid_res=0, dtype=DTYPE_F32):
     return list(offs)
 
 
-REFINE_FORMS = {"auto": -1, "lane": 0, "wave": 1, "tile": 2}
+REFINE_FORMS = {"auto": -1, "lane": 0, "wave": 1, "tile": 2, "plain": 3}
 
 
 def set_refine_form(form):
-    """Refine form for later calls: "auto" (per call), "lane" or "wave"."""
+    """Refine form for later calls: "auto" (per call), "lane", "wave", "tile" or
+    "plain" (the lane form without the minimum-corner screen)."""
     _check(lib().skycell_set_refine_form(REFINE_FORMS[form]))
 
 

@@ -178,11 +178,35 @@ struct CellEmitter {
         }
         const uint32_t it = (uint32_t)(v >> 32);
         const uint32_t ibase = (uint32_t)(prefix >> 32);
-        for (uint32_t t = 0; t < it; ++t) {
-            const uint32_t first = t * per_item;
-            const uint32_t c = (m - first) < per_item ? (m - first) : per_item;
-            items[ibase + t] = make_uint2(start + first, (c << 26) | (uint32_t)x);
+        const uint32_t own = it < kLaneItems ? it : kLaneItems;
+        for (uint32_t t = 0; t < own; ++t) put(ibase, start, m, (uint32_t)x, t);
+        // A cell with more items than one lane writes alone (on correlated data
+        // a few cells can hold most of the points, thousands of items each) is
+        // finished by every active lane of the wave together, consecutive lanes
+        // on consecutive items.  The emitter may be called from a partly active
+        // wave (the scan's last tile), so the stride is the active lane count.
+        const uint64_t act = __ballot(1);
+        uint64_t big = __ballot(it > kLaneItems);
+        const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+        const uint32_t nact = (uint32_t)__builtin_popcountll(act);
+        while (big != 0ull) {
+            const int l = __builtin_ctzll(big);
+            big &= big - 1ull;
+            const uint32_t bb = __builtin_amdgcn_readlane(ibase, l);
+            const uint32_t bs = __builtin_amdgcn_readlane(start, l);
+            const uint32_t bm = __builtin_amdgcn_readlane(m, l);
+            const uint32_t bx = __builtin_amdgcn_readlane((uint32_t)x, l);
+            const uint32_t bi = __builtin_amdgcn_readlane(it, l);
+            for (uint32_t t = kLaneItems + pos; t < bi; t += nact) put(bb, bs, bm, bx, t);
         }
+    }
+    static constexpr uint32_t kLaneItems = 8;
+    __device__ void put(uint32_t ibase, uint32_t start, uint32_t m, uint32_t x, uint32_t t) const
+    {
+        const uint32_t first = t * per_item;
+        const uint32_t c = (m - first) < per_item ? (m - first) : per_item;
+        items[ibase + t] = make_uint2(start + first, (c << 26) | x);
     }
 };
 

@@ -63,6 +63,7 @@ struct GridDesc {
     int32_t m;                 // query points per refine work item (1, 2 or 4)
     int32_t parts;             // wave form: waves that share one item's cone (>= 1)
     int32_t tile;              // 1: tile form of the refine (refine_tile.hip)
+    int32_t plain;             // 1: lane form without the walk records' minimum corners
 };
 
 // Index of the cell one column lower / higher in the dimension whose bits are
@@ -104,7 +105,42 @@ struct Workspace {
     uint64_t *survbits;   // [cells / 64 + 1] bit x: cell x is a surviving non-empty cell
     uint32_t *bcur;       // [kMaxScatterBuckets * kNumXcd] staging cursors of the two-pass scatter
     uint32_t *stage;      // [n * ((d + 6) & ~3)] staged rows of the two-pass scatter (large n only)
+    uint64_t *wrec;       // [2 * cells] walk records of the lane refine (d <= kWrecMaxD only)
 };
+
+// Walk records of the lane refine, d <= kWrecMaxD: two words per cell x.
+//   word 2x+1: bits 7k..7k+5 hold the minimum over the surviving points of
+//     cell x of their screening column in dimension k halved (6 bits); bit
+//     7k+6 is zero (a guard bit for fieldwise subtraction); 63 in every field
+//     of the d dimensions for a cell without surviving points.
+//   word 2x: bits 0..55 the fieldwise minimum of word 2y+1 over the cells y
+//     that equal x outside the first P dimensions and are <= x in those
+//     (P = wrec_prefix_dims(d, r)); bits 56..63 the lower-neighbour mask of
+//     the cell record.
+// A point of cell y can only dominate a point whose halved screening columns
+// are all >= y's minima, so the refine's cone walk loads a cell's record and
+// candidates only when that holds for some query point of its item; and when
+// the walk arrives at y by a step along dimension j < P, the part of the cone
+// it would walk below y (lower only in dimensions 0..j) is skipped entirely
+// unless word 2y passes that test.
+constexpr int kWrecMaxD = 8;
+__host__ __device__ constexpr uint64_t wrec_guards()
+{
+    uint64_t gm = 0ull;
+    for (int k = 0; k < kWrecMaxD; ++k) gm |= 1ull << (7 * k + 6);
+    return gm;
+}
+constexpr uint64_t kWrecFields = 0x00FFFFFFFFFFFFFFull;
+// Index bits of one tile of the prefix pass (its values fill 2^12 * 8 bytes of LDS).
+constexpr int kWrecTileBits = 12;
+// Dimensions of the prefix in word 2x: the first P dimensions, all their r
+// index bits in one LDS tile, at most 4.
+__host__ __device__ constexpr int wrec_prefix_dims(int d, int r)
+{
+    const int p = d < 4 ? d : 4;
+    const int fit = r < 1 ? 0 : kWrecTileBits / r;
+    return p < fit ? p : fit;
+}
 
 // Two-pass scatter, for large inputs.  Pass 1 groups the surviving points by
 // ranges of 2^sh consecutive cells ("buckets") into a staging array whose
@@ -152,6 +188,9 @@ hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *s
                             bool recount = false);
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                           const Workspace &ws, int value_bits, int num_cus, hipStream_t st);
+// Walk records of the lane form (d <= kWrecMaxD), built from the sorted points;
+// launch_scatter ends with it.
+hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, hipStream_t st);
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st);
 hipError_t refine_prepare(const GridDesc &gd);

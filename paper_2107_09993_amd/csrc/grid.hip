@@ -9,7 +9,8 @@
 //       work items;
 //   K4  scatter of surviving points, grouped by cell, as order-preserving keys
 //       (one pass below 2^20 points; above, staged by ranges of cells first so
-//       that the final writes complete whole cache lines).
+//       that the final writes complete whole cache lines), followed for d <= 8
+//       by the walk records of the refine's lane form (refine.hip).
 #include <cstdlib>
 
 #include "cellops.h"
@@ -74,6 +75,28 @@ hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats,
 }
 
 // ------------------------------------------------------------------ K1
+// Each thread quantises kQuantPer points (strided by the workgroup size, so
+// every load is coalesced) and takes each point's rank inside its cell from
+// the cell's counter.  Ranks only need to be distinct and below the cell's
+// count (the scatter puts a point at the cell's first position plus its rank),
+// so points that share a cell can take them together:
+//   * lanes of one wave whose points share a cell (common when a few cells
+//     hold most points, as on correlated data, where one counter per hot cell
+//     would otherwise take every point's atomic in turn) rank among
+//     themselves in lane order, and their leader adds their number at once.
+//     The rounds stop at the first cell held by one lane only; every lane still
+//     pending then takes its own atomic on the global counter, so distinct
+//     cells (the anti-correlated headline) pay one ballot round;
+//   * the leaders add into a small table of the workgroup's shared cells in
+//     LDS instead of the global counter, and after the workgroup's last point
+//     one atomic per table entry reserves the entry's ranks in the global
+//     counter.  A cell that finds no free entry in two probes goes to the
+//     global counter directly.
+constexpr int kQuantPer = 8;
+constexpr int kHotSlots = 128;
+constexpr uint32_t kNoSlot = 0xFFu;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict__ pts, uint32_t n,
                                                             GridDesc gd, int value_bits,
@@ -82,26 +105,81 @@ __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict_
                                                             uint32_t *__restrict__ cnt,
                                                             uint32_t *__restrict__ ctr)
 {
-    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
+    __shared__ uint32_t s_key[kHotSlots], s_cnt[kHotSlots], s_base[kHotSlots];
+    for (int e = threadIdx.x; e < kHotSlots; e += kThreads) {
+        s_key[e] = kEmptyKey;
+        s_cnt[e] = 0u;
+    }
+    __syncthreads();
+    const uint32_t lane = __lane_id();
+    const uint32_t first = blockIdx.x * (uint32_t)(kThreads * kQuantPer) + threadIdx.x;
+    uint32_t rk[kQuantPer], sl[kQuantPer];
     bool nan = false;
-    const uint32_t cell = point_cell(pts, n, i, gd, value_bits, nan);
-    cell_of[i] = cell;
-    rank[i] = atomicAdd(&cnt[cell], 1u);
+#pragma unroll
+    for (int p = 0; p < kQuantPer; ++p) {
+        const uint32_t i = first + (uint32_t)(p * kThreads);
+        const bool live = i < n;
+        uint32_t cell = 0u;
+        if (live) {
+            cell = point_cell(pts, n, i, gd, value_bits, nan);
+            cell_of[i] = cell;
+        }
+        uint64_t pend = __ballot(live);
+        bool got = false;
+        uint32_t r = 0u, slot = kNoSlot;
+        while (pend != 0ull) {
+            const int lead = __builtin_ctzll(pend);
+            const uint32_t lc = __builtin_amdgcn_readlane(cell, lead);
+            const uint64_t same = __ballot(live && !got && cell == lc);
+            const uint32_t k = (uint32_t)__builtin_popcountll(same);
+            if (k < 2u) break;
+            uint32_t base = 0u, ls = kNoSlot;
+            if (lane == (uint32_t)lead) {
+                uint32_t h = (lc * 0x9E3779B1u) >> 25;  // 7 bits: kHotSlots entries
+                for (int probe = 0; probe < 2 && ls == kNoSlot; ++probe) {
+                    const uint32_t old = atomicCAS(&s_key[h], kEmptyKey, lc);
+                    if (old == kEmptyKey || old == lc) ls = h;
+                    h = (h + 1u) & (kHotSlots - 1);
+                }
+                base = ls != kNoSlot ? atomicAdd(&s_cnt[ls], k) : atomicAdd(&cnt[lc], k);
+            }
+            base = __builtin_amdgcn_readlane(base, lead);
+            ls = __builtin_amdgcn_readlane(ls, lead);
+            if ((same >> lane) & 1ull) {
+                r = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+                slot = ls;
+                got = true;
+            }
+            pend &= ~same;
+        }
+        if (live && !got) r = atomicAdd(&cnt[cell], 1u);
+        if (live && slot == kNoSlot) rank[i] = r;
+        rk[p] = r;
+        sl[p] = slot;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kHotSlots; e += kThreads)
+        if (s_key[e] != kEmptyKey) s_base[e] = atomicAdd(&cnt[s_key[e]], s_cnt[e]);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kQuantPer; ++p) {
+        const uint32_t i = first + (uint32_t)(p * kThreads);
+        if (i < n && sl[p] != kNoSlot) rank[i] = s_base[sl[p]] + rk[p];
+    }
     if (nan) atomicOr(&ctr[kCtrErr], 1u);
 }
 
 hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                                 int value_bits, const Workspace &ws, hipStream_t st)
 {
+    const dim3 grid = grid_for(n, kThreads * kQuantPer);
     if (dtype == SKYCELL_DTYPE_F32)
-        hipLaunchKernelGGL(k_quantize_hist<float>, grid_for(n), dim3(kThreads), 0, st,
-                           (const float *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.rank,
-                           ws.cnt, ws.ctr);
+        hipLaunchKernelGGL(k_quantize_hist<float>, grid, dim3(kThreads), 0, st, (const float *)pts, (uint32_t)n, gd,
+                           value_bits, ws.cell_of, ws.rank, ws.cnt, ws.ctr);
     else
-        hipLaunchKernelGGL(k_quantize_hist<uint16_t>, grid_for(n), dim3(kThreads), 0, st,
-                           (const uint16_t *)pts, (uint32_t)n, gd, value_bits, ws.cell_of, ws.rank,
-                           ws.cnt, ws.ctr);
+        hipLaunchKernelGGL(k_quantize_hist<uint16_t>, grid, dim3(kThreads), 0, st, (const uint16_t *)pts,
+                           (uint32_t)n, gd, value_bits, ws.cell_of, ws.rank, ws.cnt, ws.ctr);
     return hipGetLastError();
 }
 
@@ -496,8 +574,8 @@ static hipError_t launch_scatter_two_pass(const T *pts, int64_t n, const GridDes
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
-                          const Workspace &ws, int value_bits, int num_cus, hipStream_t st)
+static hipError_t launch_scatter_points(const void *pts, int dtype, int64_t n, const GridDesc &gd,
+                                        const Workspace &ws, int value_bits, int num_cus, hipStream_t st)
 {
     if (ws.stage != nullptr && scatter_two_pass_enabled()) {
         if (dtype == SKYCELL_DTYPE_F32)
@@ -513,6 +591,14 @@ hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc 
                            (const uint16_t *)pts, (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank,
                            ws.rec, ws.keys, ws.fkeys, ws.sidx, ws.flag, scatter_live_flag(gd));
     return hipGetLastError();
+}
+
+hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
+                          const Workspace &ws, int value_bits, int num_cus, hipStream_t st)
+{
+    const hipError_t e = launch_scatter_points(pts, dtype, n, gd, ws, value_bits, num_cus, st);
+    if (e != hipSuccess) return e;
+    return launch_walk_records(gd, ws, st);
 }
 
 // ------------------------------------------------------------------ scan partials

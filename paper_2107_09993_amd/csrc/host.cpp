@@ -148,7 +148,7 @@ static int items_per_lane(int d)
 // tuning table's form for this (d, n, dtype) and grid, else the wave form when
 // the grid is very coarse (at least 32 points per cell of the index space on
 // average), where cells hold enough points to keep a wave busy.
-static std::atomic<int> g_form_override{-2};  // -2 unread, -1 none, 0 lane, 1 wave, 2 tile
+static std::atomic<int> g_form_override{-2};  // -2 unread, -1 none, 0 lane, 1 wave, 2 tile, 3 plain lane
 
 static int refine_form(int64_t n, int d, int g, int dtype)
 {
@@ -156,7 +156,11 @@ static int refine_form(int64_t n, int d, int g, int dtype)
     if (ov == -2) {
         const char *v = getenv("SKYCELL_REFINE_FORM");
         const int e = v == nullptr ? -1
-                      : (strcmp(v, "wave") == 0 ? 1 : (strcmp(v, "lane") == 0 ? 0 : (strcmp(v, "tile") == 0 ? 2 : -1)));
+                      : (strcmp(v, "wave") == 0   ? 1
+                         : strcmp(v, "lane") == 0   ? 0
+                         : strcmp(v, "tile") == 0   ? 2
+                         : strcmp(v, "plain") == 0  ? 3
+                                                    : -1);
         int expected = -2;
         g_form_override.compare_exchange_strong(expected, e);
         ov = g_form_override.load();
@@ -228,6 +232,7 @@ GridDesc pipeline_desc(int64_t n, int d, int g, int dtype)
         gd.tile = 1;
         return gd;
     }
+    if (form == 3) gd.plain = 1;
     if (form == 1) {
         gd.m = kWaveItemPoints;
         // items <= n, and items * parts work units must stay below 2^31
@@ -281,6 +286,7 @@ size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *b
     w.survbits = (uint64_t *)take(8 * ((size_t)cells / 64 + 1));
     w.bcur = (uint32_t *)take(4 * (size_t)kMaxScatterBuckets * kNumXcd);
     w.stage = scatter_two_pass(n) ? (uint32_t *)take(4 * nn * (size_t)(((unsigned)d + 6u) & ~3u)) : nullptr;
+    w.wrec = d <= kWrecMaxD ? (uint64_t *)take(16 * (size_t)cells) : nullptr;
     if (ws) *ws = w;
     return off;
 }
@@ -556,7 +562,7 @@ int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res)
 
 int skycell_set_refine_form(int32_t form)
 {
-    if (form < -1 || form > 2) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0, 1 or 2", form);
+    if (form < -1 || form > 3) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0, 1, 2 or 3", form);
     g_form_override.store(form);
     return ok();
 }

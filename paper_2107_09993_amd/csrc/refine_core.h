@@ -238,27 +238,28 @@ __device__ void refine_loop(const RefineView &v, Feeder &feed, uint32_t &visits,
             ++visits;
         }
 
-        // ---- deferred exact test (Definition 1), branch-free over the query
-        // points: e dominates q iff no coordinate of e exceeds q's (max(e,q) ^ q
-        // is zero in every dimension) and some coordinate differs
+        // ---- deferred exact test (Definition 1) of one flagged query point per
+        // turn, the lowest: e dominates q iff no coordinate of e exceeds q's
+        // (max(e,q) ^ q is zero in every dimension) and some coordinate differs.
+        // Another flagged point keeps the slot, and the candidate's keys are
+        // loaded again, for the next turn.
         if (exok) {
-            uint32_t dom = 0u;
+            exmask &= alive;
+            const uint32_t tb = exmask & (0u - exmask);
+            uint32_t gt = 0u, ne = 0u;
 #pragma unroll
-            for (int t = 0; t < M; ++t) {
-                uint32_t gt = 0u, ne = 0u;
+            for (int k = 0; k < D; ++k) {
+                uint32_t qv = q[0][k];
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const uint32_t qv = q[t][k];
-                    uint32_t g = max(e[k], qv) ^ qv, x = e[k] ^ qv;
-                    opaque(g);
-                    opaque(x);
-                    gt |= g;
-                    ne |= x;
-                }
-                dom |= (gt == 0u && ne != 0u) ? (1u << t) : 0u;
+                for (int t = 1; t < M; ++t) qv = tb == (1u << t) ? q[t][k] : qv;
+                uint32_t g = max(e[k], qv) ^ qv, x = e[k] ^ qv;
+                opaque(g);
+                opaque(x);
+                gt |= g;
+                ne |= x;
             }
-            alive &= ~(dom & exmask);
-            exmask = 0u;
+            if (gt == 0u && ne != 0u) alive &= ~tb;
+            exmask &= ~tb;
         }
 
         // ---- screening of up to two candidates.  Per byte, (p | 0x80) - q has its

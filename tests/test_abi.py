@@ -141,6 +141,15 @@ def test_wave_parts_argument_errors():
     sky.set_wave_parts(0)
 
 
+def test_refine_form_argument_errors():
+    lib = sky.lib()
+    for bad in (-2, 4):
+        assert lib.skycell_set_refine_form(bad) == sky.E_INVAL
+    for form in sky.REFINE_FORMS:
+        sky.set_refine_form(form)
+    sky.set_refine_form("auto")
+
+
 def test_batched_plan_argument_errors():
     import numpy as np
     lib = sky.lib()

@@ -1,6 +1,8 @@
-"""Both refine forms (lane: one lane walks the cone of a few points of one
-cell; wave: one wave walks the cone of up to 63 points of one cell) give the
-oracle's skyline on the same inputs, fine and coarse grids alike."""
+"""The refine forms (lane: one lane walks the cone of a few points of one
+cell, passing over cells whose minimum corner rules them out for d <= 8;
+plain: the lane form without that screen; wave: one wave walks the cone of up
+to 63 points of one cell) give the oracle's skyline on the same inputs, fine
+and coarse grids alike."""
 import numpy as np
 import pytest
 import torch
@@ -21,7 +23,20 @@ def _run(x, g, value_bits=10, stats=False):
     return (out, s.stats_dict()) if stats else out
 
 
+def _hot(n, d, seed):
+    """Most points in a few cells: a narrow diagonal band plus a third of the rows
+    copied from five points (many lanes of one wave land in one cell, and some
+    cells hold thousands of refine items)."""
+    rng = np.random.default_rng(seed)
+    x = datagen.correlated(n, d, seed, sigma=0.01)
+    rows = rng.choice(n, size=n // 3, replace=False)
+    x[rows] = x[rng.integers(0, n, size=5)][rng.integers(0, 5, size=rows.size)]
+    return x
+
+
 CASES = [
+    ("hot_d4_g2", lambda: _hot(60_000, 4, seed=9), 2),
+    ("hot_d3_g8", lambda: _hot(60_000, 3, seed=10), 8),
     ("ind_d3_coarse", lambda: datagen.independent(30_000, 3, seed=1), 2),
     ("anti_d8_coarse", lambda: datagen.anticorrelated(20_000, 8, seed=2), 2),
     ("anti_d8_fine", lambda: datagen.anticorrelated(20_000, 8, seed=2), 8),
@@ -31,10 +46,35 @@ CASES = [
     ("ind_d16", lambda: datagen.independent(10_000, 16, seed=6), 2),
     ("ind_d2_one_cell", lambda: datagen.independent(100_000, 2, seed=7), 1),
     ("anti_d10_g3", lambda: datagen.anticorrelated(30_000, 10, seed=8), 3),
+    # half of the points in the top screening column of every dimension: their
+    # walks pass every cell, empty ones included (whose minima are the "no
+    # points" value 63, equal to their halved columns)
+    ("top_column_d4", lambda: _top_column(20_000, 4, seed=11), 8),
+    # one cell with more points than a cell record's count field holds (the
+    # count is read from the next cell's first position), and more than one
+    # lane reduces alone when the walk records are built
+    ("saturated_cell_d3", lambda: _one_cell(40_000, 3, seed=12), 4),
+    ("anti_d7_g6", lambda: datagen.anticorrelated(50_000, 7, seed=13), 6),
 ]
 
 
-@pytest.mark.parametrize("form", ["lane", "wave"])
+def _top_column(n, d, seed):
+    """Uniform points, half of them moved into [127/128, 1] in every
+    coordinate (screening column 127)."""
+    x = datagen.independent(n, d, seed)
+    top = x[: n // 2] * np.float32(1.0 / 128.0) + np.float32(127.0 / 128.0)
+    x[: n // 2] = np.minimum(top, np.float32(1.0))
+    return x
+
+
+def _one_cell(n, d, seed):
+    """n points inside one cell of a 4-column grid, with repeated rows."""
+    x = datagen.independent(n, d, seed) * np.float32(0.2) + np.float32(0.3)
+    x[n // 2:] = x[: n - n // 2][::-1]
+    return x
+
+
+@pytest.mark.parametrize("form", ["lane", "plain", "wave"])
 @pytest.mark.parametrize("name,make,g", CASES, ids=[c[0] for c in CASES])
 def test_refine_form_matches_oracle(oracle_mod, form, name, make, g):
     x = make()
