@@ -141,6 +141,29 @@ CONFIGS = {
 }
 
 
+def tuned_config(sky, soa, grid):
+    """The configuration a grid_res = 0 call uses on this input: its input class
+    from a sample on the device, then the tuning table's grid, refine form and
+    waves per item for that class (chosen once per workload, as a caller with a
+    persistent workspace would).  With an explicit grid: that grid and the
+    library's form choice."""
+    import torch
+    d, n = soa.shape
+    if grid:
+        return {"grid": grid, "form": None, "parts": 0, "input_class": None}
+    cls = sky.input_class(soa)
+    dtype = sky.DTYPE_U16 if soa.dtype == torch.uint16 else sky.DTYPE_F32
+    g, form, parts = sky.choose_config(n, d, dtype, cls)
+    return {"grid": g, "form": form, "parts": parts, "input_class": sky.CLASS_NAMES[cls]}
+
+
+def apply_config(sky, cfg):
+    """Force the configuration's refine form and waves per item (None: the
+    library's per-call choice)."""
+    sky.set_refine_form(cfg["form"] or "auto")
+    sky.set_wave_parts(cfg["parts"] if cfg["form"] == "wave" else 0)
+
+
 def single_bench(x, grid, steps, warmup, dev, value_bits=10):
     """Times `steps` calls of the whole path on resident data (one host sync per
     call, as in the headline); returns points/s, tests/s and bandwidth."""
@@ -150,7 +173,17 @@ def single_bench(x, grid, steps, warmup, dev, value_bits=10):
     n, d = x.shape
     dtype = "u16" if x.dtype == np.uint16 else "f32"
     soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
-    g = grid if grid else sky.choose_grid(n, d, sky.DTYPE_U16 if dtype == "u16" else sky.DTYPE_F32)
+    cfg = tuned_config(sky, soa, grid)
+    apply_config(sky, cfg)
+    try:
+        res = _single_bench(sky, torch, soa, n, d, dtype, cfg["grid"], steps, warmup, dev, value_bits)
+    finally:
+        apply_config(sky, {"form": None, "parts": 0})
+    res["config"] = cfg
+    return res
+
+
+def _single_bench(sky, torch, soa, n, d, dtype, g, steps, warmup, dev, value_bits):
     probe = sky.Skyline(n, d, dtype=dtype, grid_res=g, value_bits=value_bits, device=dev, stats=True)
     probe.run(soa)
     count = int(probe.result().numel())
@@ -247,7 +280,6 @@ def cpu_baseline(x_host, sample):
 def phase_bytes(n, d, cells, st):
     """Bytes each streaming phase must move at least with this data layout
     (reads + writes, every array touched once), for the per-phase bandwidth."""
-    r = max(1, (cells.bit_length() - 1) // d)
     fw = 8 * ((d + 7) // 8)
     surv = st["survivor_points"]
     # walk records are built for the lane form only (its items hold at most two
@@ -256,12 +288,12 @@ def phase_bytes(n, d, cells, st):
     return {
         # zero the counts; read the coordinates, write cell and rank per point
         "quantize_hist": 4 * cells + n * (4 * d + 8),
-        # counts -> occupancy bits; prefix-OR steps over the bitmap (one pass
-        # inside words, one per column bit above: read two words, write one);
-        # counts and records
-        "cell_prune": cells * (4 + 8) + (cells // 8) * (1 + 2 + max(0, r * d - 6) * 3 // 2),
-        # reduce and emit passes over (record, count), start words, work items
-        "cell_scan": cells * (12 + 12 + 4) + st["items"] * 8,
+        # counts read, records written, the lower-closure bitmap written and
+        # read once, the bitmap of surviving cells written
+        "cell_prune": cells * (4 + 8) + (cells // 8) * 3,
+        # record and count read, first sorted position written per cell; the
+        # work items written
+        "cell_scan": cells * (8 + 4 + 4) + st["items"] * 8,
         # coordinates, cell, rank, record per point; keys, screening words,
         # original index of surviving points; flag of every point; then for
         # d <= 8 the walk records (read the cell records and the screening
@@ -301,7 +333,9 @@ def main():
     x = datagen.generate(a.dist, a.n, a.d, a.seed)
     soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
     progress("headline input generated and resident: %s n=%d d=%d" % (a.dist, a.n, a.d))
-    g = a.grid if a.grid else sky.choose_grid(a.n, a.d)
+    cfg = tuned_config(sky, soa, a.grid)
+    g = cfg["grid"]
+    apply_config(sky, cfg)
 
     # one call with counters for the algorithmic work figures
     probe = sky.Skyline(a.n, a.d, grid_res=g, device=dev, stats=True)
@@ -329,6 +363,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sky.profile_enable(False)
+    apply_config(sky, {"form": None, "parts": 0})
     if c != sky_count:
         print("skyline size changed between calls: %d vs %d" % (c, sky_count), file=sys.stderr)
         sys.exit(1)
@@ -368,7 +403,7 @@ def main():
            "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": workload, "n": a.n, "d": a.d, "distribution": a.dist,
-                      "grid_res": g, "skyline": sky_count},
+                      "grid_res": g, "input_class": cfg["input_class"], "skyline": sky_count},
            "phases_ms": phases,
            "phases_hbm": phase_hbm,
            "dominance_tests_per_s": st["pair_tests"] / (ms_per_step * 1e-3),

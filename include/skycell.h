@@ -173,10 +173,45 @@ int skycell_compute_static(const void *points, int32_t dtype, int64_t n, int32_t
 int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res);
 
 /*
- * Load an autotuner table (text, one "d log2n dtype g [form [parts]]" line per
- * entry, form 0 = lane, 1 = wave refine, see skycell_set_refine_form; parts
- * the wave form's waves per item, see skycell_set_wave_parts; '#' starts a
- * comment line).  dtype is SKYCELL_DTYPE_* for single calls and
+ * Input classes of the tuning table: whether the attributes of the input rise
+ * together, trade off against each other, or neither.  The skyline's size and
+ * the cost of each grid and refine form depend mostly on this.
+ */
+#define SKYCELL_CLASS_INDEPENDENT 0
+#define SKYCELL_CLASS_CORRELATED 1
+#define SKYCELL_CLASS_ANTICORRELATED 2
+
+/*
+ * Input class of n points in d attributes (device, SoA [d][n], as for
+ * skycell_compute; dtype SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16), from the
+ * mean correlation of two attributes over a strided sample of at most 65,536
+ * points: > 0.3 correlated, < -0.3/(d-1) anti-correlated, else independent
+ * (d = 1: independent).  Enqueued on `stream`, then waits for `stream`: the
+ * call returns with *cls set.  Returns SKYCELL_E_INVAL for bad arguments or a
+ * stream under graph capture.
+ */
+int skycell_input_class(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t *cls, void *stream);
+
+/*
+ * The configuration a call with grid_res = 0 uses for an input of class cls
+ * (-1: not known): grid resolution, refine form (0 lane, 1 wave, as in
+ * skycell_set_refine_form) and, for the wave form, waves per item (else 0).
+ * Table rows tuned on class cls are preferred, then rows for any class (the
+ * lowest mean time over the three classes), then the rules of
+ * skycell_choose_grid and skycell_set_refine_form.  skycell_compute and
+ * skycell_compute_u16 with grid_res = 0 compute the input's class themselves
+ * (skycell_input_class, one synchronisation of the stream) when the table
+ * holds class rows for d, dtype and about n, and n >= 65,536.
+ */
+int skycell_choose_config(int64_t n, int32_t d, int32_t dtype, int32_t cls, int32_t *grid_res, int32_t *form,
+                          int32_t *parts);
+
+/*
+ * Load an autotuner table (text, one "d log2n dtype g [form [parts [class]]]"
+ * line per entry, form 0 = lane, 1 = wave refine, see skycell_set_refine_form;
+ * parts the wave form's waves per item, see skycell_set_wave_parts; class the
+ * SKYCELL_CLASS_* input class the row was tuned on, absent or -1 for rows
+ * chosen over all classes; '#' starts a comment line).  dtype is SKYCELL_DTYPE_* for single calls and
  * SKYCELL_DTYPE_* + 2 for the instances of a batched plan.  NULL clears the
  * table.  Applies to all later calls in the process.  The Python binding loads
  * the table shipped with the package unless SKYCELL_NO_TUNING is set.

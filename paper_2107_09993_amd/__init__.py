@@ -57,6 +57,9 @@ def lib():
     L.skycell_compute_ws.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, sz, p, p]
     L.skycell_compute_static.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, p]
     L.skycell_choose_grid.argtypes = [i64, i32, i32, ctypes.POINTER(i32)]
+    L.skycell_input_class.argtypes = [p, i32, i64, i32, ctypes.POINTER(i32), p]
+    L.skycell_choose_config.argtypes = [i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i32)]
     L.skycell_load_tuning.argtypes = [ctypes.c_char_p]
     L.skycell_set_refine_form.argtypes = [i32]
     L.skycell_set_wave_parts.argtypes = [i32]
@@ -102,6 +105,7 @@ def lib():
     L.skycell_last_error.restype = ctypes.c_char_p
     for name in ("skycell_compute", "skycell_compute_u16", "skycell_workspace_bytes",
                  "skycell_compute_ws", "skycell_compute_static", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
+                 "skycell_input_class", "skycell_choose_config",
                  "skycell_set_wave_parts", "skycell_set_pivot_gate", "skycell_set_cell_prune",
                  "skycell_shrink_tree", "skycell_compute_layered",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
@@ -142,6 +146,33 @@ def choose_grid(n, d, dtype=DTYPE_F32):
     g = ctypes.c_int32(0)
     _check(lib().skycell_choose_grid(int(n), int(d), int(dtype), ctypes.byref(g)))
     return g.value
+
+
+CLASS_INDEPENDENT, CLASS_CORRELATED, CLASS_ANTICORRELATED = 0, 1, 2
+CLASS_NAMES = ("independent", "correlated", "anticorrelated")
+
+
+def input_class(points_soa, stream=None):
+    """Input class (CLASS_*) of a contiguous [d, n] CUDA tensor, float32 or
+    uint16 (skycell_input_class; waits for the stream)."""
+    import torch
+    if not points_soa.is_cuda or not points_soa.is_contiguous() or points_soa.dim() != 2:
+        raise ValueError("points must be a contiguous [d, n] CUDA tensor")
+    d, n = points_soa.shape
+    st = stream if stream is not None else torch.cuda.current_stream(points_soa.device).cuda_stream
+    c = ctypes.c_int32(-1)
+    _check(lib().skycell_input_class(ctypes.c_void_p(points_soa.data_ptr()), _dtype_code(points_soa), int(n),
+                                     int(d), ctypes.byref(c), ctypes.c_void_p(st)))
+    return c.value
+
+
+def choose_config(n, d, dtype=DTYPE_F32, cls=-1):
+    """(grid, refine form name, waves per item) a grid_res = 0 call uses for an
+    input of class cls (-1: not known), from the tuning table."""
+    g, f, p = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().skycell_choose_config(int(n), int(d), int(dtype), int(cls), ctypes.byref(g), ctypes.byref(f),
+                                       ctypes.byref(p)))
+    return g.value, ("lane", "wave")[f.value], p.value
 
 
 NUM_PHASES = 6

@@ -3,11 +3,14 @@
 For every (d, n) on a grid of shapes it times the single-instance path on the
 three synthetic distributions for each candidate grid, refine form and (for the
 wave form) number of waves per work item, and keeps, per (d, n), the choice
-with the lowest mean time (the distribution of a future input is not known
-when the grid is chosen).  The result is a text table of
-"d log2n dtype g form parts" lines that the library loads with
+with the lowest mean time, and for each input class (independent, correlated,
+anti-correlated: the library computes a call's class from a sample of its
+input, skycell_input_class) the choice fastest on that class.  The result is
+a text table of
+"d log2n dtype g form parts [class]" lines that the library loads with
 skycell_load_tuning (form: the refine form, 0 lane, 1 wave; parts: waves per
-item of the wave form):
+item of the wave form; class: for single calls, one more row per input class
+whose own fastest configuration differs from the one with the lowest mean):
 
     dtype 0 = binary32, single-instance calls (skycell_compute with grid_res 0)
     dtype 2 = binary32, instances of a batched plan
@@ -123,38 +126,50 @@ def sweep(dims, sizes, reps=2, log=print):
             max_cells = min(1 << 24, max(1 << 16, 32 * n))
             grids = candidate_grids(n, d, max_cells)
             configs = [(g, "lane", 1) for g in grids] + [(g, "wave", p) for g in grids for p in WAVE_PARTS]
-            totals = dict.fromkeys(configs, 0.0)
+            per = {dist: dict.fromkeys(configs, 0.0) for dist in datagen.DISTRIBUTIONS}
             for k, dist in enumerate(datagen.DISTRIBUTIONS):
                 x = datagen.generate(dist, n, d, seed=100 + k)
                 soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
                 for g, f, p in configs:
                     sky.set_refine_form(f)
                     sky.set_wave_parts(p)
-                    totals[(g, f, p)] += time_once(sky, torch, soa, n, d, g, reps)
+                    per[dist][(g, f, p)] = time_once(sky, torch, soa, n, d, g, reps)
                 del soa
             sky.set_refine_form("auto")
             sky.set_wave_parts(0)
+            totals = {c: sum(per[dist][c] for dist in datagen.DISTRIBUTIONS) for c in configs}
             best = min(configs, key=lambda c: totals[c])
             l2 = int(round(math.log2(n)))
             table.append((d, l2, best[0], FORMS.index(best[1]), best[2]))
+            # one more row per input class whose own best differs from the row
+            # for all classes (the class index is datagen.DISTRIBUTIONS' order)
+            for cls, dist in enumerate(datagen.DISTRIBUTIONS):
+                own = min(configs, key=lambda c: per[dist][c])
+                if own != best:
+                    table.append((d, l2, own[0], FORMS.index(own[1]), own[2], cls))
             log(json.dumps({"d": d, "n": n, "best": "%d/%s/%d" % best,
-                            "mean_ms": {"%d/%s/%d" % c: round(1e3 * t / 3, 3) for c, t in totals.items()}}))
+                            "mean_ms": {"%d/%s/%d" % c: round(1e3 * t / 3, 3) for c, t in totals.items()},
+                            "per_class_best": {dist: "%d/%s/%d" % min(configs, key=lambda c: per[dist][c])
+                                               for dist in datagen.DISTRIBUTIONS}}))
     return table
 
 
 def write_table(table, path, batched=None):
     """dtype 0 rows from the single-call sweep; dtype 2 rows from the batched
-    sweep when given, else the single-call choices."""
+    sweep when given, else the single-call choices (without class rows)."""
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
-        f.write("# d log2n dtype g form parts  -- grid resolution, refine form (0 lane, 1 wave) and\n")
+        f.write("# d log2n dtype g form parts [class]  -- grid resolution, refine form (0 lane, 1 wave) and\n")
         f.write("# waves per item of the wave form: dtype 0 with the lowest mean time of one call over\n")
-        f.write("# the independent, correlated and anti-correlated inputs, dtype 2 with the highest\n")
-        f.write("# throughput of batched plans of such instances (paper_2107_09993_amd.autotune)\n")
-        for d, l2, g, form, parts in table:
-            f.write("%d %d 0 %d %d %d\n" % (d, l2, g, form, parts))
-        for d, l2, g, form, parts in (batched if batched is not None else table):
-            f.write("%d %d 2 %d %d %d\n" % (d, l2, g, form, parts))
+        f.write("# the independent, correlated and anti-correlated inputs (with a class column: the\n")
+        f.write("# lowest time on that input class, 0 independent, 1 correlated, 2 anti-correlated),\n")
+        f.write("# dtype 2 with the highest throughput of batched plans of such instances\n")
+        f.write("# (paper_2107_09993_amd.autotune)\n")
+        for row in table:
+            f.write("%d %d 0 %d %d %d" % (row[0], row[1], row[2], row[3], row[4]))
+            f.write(" %d\n" % row[5] if len(row) > 5 else "\n")
+        for row in (batched if batched is not None else [r for r in table if len(r) == 5]):
+            f.write("%d %d 2 %d %d %d\n" % tuple(row[:5]))
 
 
 def main():

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libskycell.so")
 
-SOURCES = ["grid.hip", "refine.hip", "refine_wave.hip", "refine_tile.hip", "output.hip", "mlp.hip", "pivot.hip", "static_scratch.hip", "dynamic.hip", "quadrant.hip", "shrink_tree.hip", "fine_layer.hip", "host.cpp", "batched_host.cpp", "learned_host.cpp"]
+SOURCES = ["grid.hip", "refine.hip", "walk_records.hip", "input_class.hip", "refine_wave.hip", "refine_tile.hip", "output.hip", "mlp.hip", "pivot.hip", "static_scratch.hip", "dynamic.hip", "quadrant.hip", "shrink_tree.hip", "fine_layer.hip", "host.cpp", "batched_host.cpp", "learned_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -188,8 +188,11 @@ hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *s
                             bool recount = false);
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                           const Workspace &ws, int value_bits, int num_cus, hipStream_t st);
-// Walk records of the lane form (d <= kWrecMaxD), built from the sorted points;
-// launch_scatter ends with it.
+// The lane form of the refine reads walk records (d <= kWrecMaxD unless the
+// plain lane form was asked for).
+inline bool lane_mc(const GridDesc &gd) { return gd.d <= kWrecMaxD && gd.plain == 0; }
+// Walk records of the lane form (walk_records.hip), built from the sorted
+// points; launch_scatter ends with it.
 hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, hipStream_t st);
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st);

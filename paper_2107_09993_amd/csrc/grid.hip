@@ -84,15 +84,17 @@ hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats,
 //     hold most points, as on correlated data, where one counter per hot cell
 //     would otherwise take every point's atomic in turn) rank among
 //     themselves in lane order, and their leader adds their number at once.
-//     The rounds stop at the first cell held by one lane only; every lane still
-//     pending then takes its own atomic on the global counter, so distinct
-//     cells (the anti-correlated headline) pay one ballot round;
+//     A round whose lowest pending lane holds its cell alone leaves that lane
+//     to its own atomic on the global counter; after kQuantSkips such rounds
+//     every lane still pending takes its own atomic, so wholly distinct cells
+//     (the anti-correlated headline) pay a few ballot rounds;
 //   * the leaders add into a small table of the workgroup's shared cells in
 //     LDS instead of the global counter, and after the workgroup's last point
 //     one atomic per table entry reserves the entry's ranks in the global
 //     counter.  A cell that finds no free entry in two probes goes to the
 //     global counter directly.
 constexpr int kQuantPer = 8;
+constexpr int kQuantSkips = 6;
 constexpr int kHotSlots = 128;
 constexpr uint32_t kNoSlot = 0xFFu;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
@@ -127,12 +129,17 @@ __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict_
         uint64_t pend = __ballot(live);
         bool got = false;
         uint32_t r = 0u, slot = kNoSlot;
-        while (pend != 0ull) {
+        int skips = 0;
+        while (pend != 0ull && skips < kQuantSkips) {
             const int lead = __builtin_ctzll(pend);
             const uint32_t lc = __builtin_amdgcn_readlane(cell, lead);
             const uint64_t same = __ballot(live && !got && cell == lc);
             const uint32_t k = (uint32_t)__builtin_popcountll(same);
-            if (k < 2u) break;
+            pend &= ~same;
+            if (k < 2u) {
+                ++skips;
+                continue;
+            }
             uint32_t base = 0u, ls = kNoSlot;
             if (lane == (uint32_t)lead) {
                 uint32_t h = (lc * 0x9E3779B1u) >> 25;  // 7 bits: kHotSlots entries
@@ -151,7 +158,6 @@ __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict_
                 slot = ls;
                 got = true;
             }
-            pend &= ~same;
         }
         if (live && !got) r = atomicAdd(&cnt[cell], 1u);
         if (live && slot == kNoSlot) rank[i] = r;

@@ -52,9 +52,34 @@ struct TuneEntry {
     int g;
     int form;   // refine form for this grid: 0 lane, 1 wave, -1 not given
     int parts;  // wave form: waves per item, 0 not given
+    int cls;    // input class (SKYCELL_CLASS_*) the row was tuned on, -1 any
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
+
+// The table row for d and n among the rows `want` accepts, with the nearest
+// log2 n no more than max_dist away: rows tuned on input class cls first (when
+// cls >= 0), else rows for any class.  The caller holds g_tune_mu.
+template <class Want>
+static const TuneEntry *tune_row(int d, int64_t n, int cls, int max_dist, Want want)
+{
+    const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
+    for (int pass = cls >= 0 ? 0 : 1; pass < 2; ++pass) {
+        const TuneEntry *best = nullptr;
+        int best_dist = 1 << 30;
+        for (const TuneEntry &e : g_tune) {
+            if (e.d != d || !want(e)) continue;
+            if (pass == 0 ? e.cls != cls : e.cls >= 0) continue;
+            const int dist = std::abs(e.log2n - l2);
+            if (dist < best_dist) {
+                best_dist = dist;
+                best = &e;
+            }
+        }
+        if (best != nullptr && best_dist <= max_dist) return best;
+    }
+    return nullptr;
+}
 
 // Index bits per dimension for g columns: ceil(log2 g).
 static int index_bits(int g)
@@ -92,18 +117,9 @@ int choose_grid_batched(int64_t n, int d, int dtype)
 {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        int best = -1, best_dist = 1 << 30;
-        const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
-        for (const TuneEntry &e : g_tune) {
-            if (e.d != d || e.dtype != dtype + 2) continue;
-            const int dist = std::abs(e.log2n - l2);
-            if (dist < best_dist) {
-                best_dist = dist;
-                best = e.g;
-            }
-        }
+        const TuneEntry *e = tune_row(d, n, -1, 2, [&](const TuneEntry &t) { return t.dtype == dtype + 2; });
         const uint64_t cap = std::min<uint64_t>(1u << 24, std::max<uint64_t>(1u << 16, (uint64_t)n * 32u));
-        if (best >= 1 && best_dist <= 2 && grid_cells(best, d) <= cap) return best;
+        if (e != nullptr && grid_cells(e->g, d) <= cap) return e->g;
     }
     double target = 2.0 * (double)n;
     if (target < 256.0) target = 256.0;
@@ -113,22 +129,25 @@ int choose_grid_batched(int64_t n, int d, int dtype)
     return g;
 }
 
-static int choose_grid(int64_t n, int d, int dtype)
+static int choose_grid(int64_t n, int d, int dtype, int cls = -1)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    int best = -1, best_dist = 1 << 30;
-    const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
-    for (const TuneEntry &e : g_tune) {
-        if (e.d != d || e.dtype != dtype) continue;
-        const int dist = std::abs(e.log2n - l2);
-        if (dist < best_dist) {
-            best_dist = dist;
-            best = e.g;
-        }
-    }
     // entries measured at sizes more than a factor ~2 away do not apply
-    if (best >= 1 && best_dist <= 1 && grid_cells(best, d) <= kMaxCells) return best;
+    const TuneEntry *e = tune_row(d, n, cls, 1, [&](const TuneEntry &t) { return t.dtype == dtype; });
+    if (e != nullptr && grid_cells(e->g, d) <= kMaxCells) return e->g;
     return default_grid(n, d);
+}
+
+// Whether the table holds rows tuned on one input class for single calls of
+// this d, dtype and about this n (then the class of the input is worth
+// computing before choosing the grid).
+static bool has_class_rows(int64_t n, int d, int dtype)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
+    for (const TuneEntry &e : g_tune)
+        if (e.d == d && e.dtype == dtype && e.cls >= 0 && std::abs(e.log2n - l2) <= 1) return true;
+    return false;
 }
 
 // Query points per refine work item: the default for d, or SKYCELL_ITEMS_PER_LANE
@@ -150,7 +169,20 @@ static int items_per_lane(int d)
 // average), where cells hold enough points to keep a wave busy.
 static std::atomic<int> g_form_override{-2};  // -2 unread, -1 none, 0 lane, 1 wave, 2 tile, 3 plain lane
 
-static int refine_form(int64_t n, int d, int g, int dtype)
+// The form the table (or the rule) gives, without the override.
+static int table_form(int64_t n, int d, int g, int dtype, int cls)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const TuneEntry *e = tune_row(d, n, cls, 2, [&](const TuneEntry &t) {
+            return t.g == g && t.form >= 0 && (t.dtype == dtype || t.dtype == dtype + 2);
+        });
+        if (e != nullptr) return e->form;
+    }
+    return (uint64_t)n >= 32ull * grid_cells(g, d) ? 1 : 0;
+}
+
+static int refine_form(int64_t n, int d, int g, int dtype, int cls)
 {
     int ov = g_form_override.load();
     if (ov == -2) {
@@ -166,21 +198,7 @@ static int refine_form(int64_t n, int d, int g, int dtype)
         ov = g_form_override.load();
     }
     if (ov >= 0) return ov;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        int best = -1, best_dist = 1 << 30;
-        const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
-        for (const TuneEntry &e : g_tune) {
-            if (e.d != d || e.g != g || e.form < 0 || (e.dtype != dtype && e.dtype != dtype + 2)) continue;
-            const int dist = std::abs(e.log2n - l2);
-            if (dist < best_dist) {
-                best_dist = dist;
-                best = e.form;
-            }
-        }
-        if (best >= 0 && best_dist <= 2) return best;
-    }
-    return (uint64_t)n >= 32ull * grid_cells(g, d) ? 1 : 0;
+    return table_form(n, d, g, dtype, cls);
 }
 
 // Waves per item of the wave form: skycell_set_wave_parts / SKYCELL_WAVE_PARTS,
@@ -198,7 +216,17 @@ static std::atomic<int> g_pivot_gate{1};
 static std::atomic<int> g_cell_prune{0};
 int cell_prune_form() { return g_cell_prune.load(); }
 
-static int wave_parts(int64_t n, int d, int g, int dtype)
+// The waves per item the table gives, without the override.
+static int table_parts(int64_t n, int d, int g, int dtype, int cls)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneEntry *e = tune_row(d, n, cls, 2, [&](const TuneEntry &t) {
+        return t.g == g && t.form == 1 && t.parts >= 1 && (t.dtype == dtype || t.dtype == dtype + 2);
+    });
+    return e != nullptr ? e->parts : 1;
+}
+
+static int wave_parts(int64_t n, int d, int g, int dtype, int cls)
 {
     int ov = g_parts_override.load();
     if (ov == -2) {
@@ -210,24 +238,13 @@ static int wave_parts(int64_t n, int d, int g, int dtype)
         ov = g_parts_override.load();
     }
     if (ov > 0) return ov;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    int best = -1, best_dist = 1 << 30;
-    const int l2 = n > 1 ? (int)std::lround(std::log2((double)n)) : 0;
-    for (const TuneEntry &e : g_tune) {
-        if (e.d != d || e.g != g || e.form != 1 || e.parts < 1 || (e.dtype != dtype && e.dtype != dtype + 2)) continue;
-        const int dist = std::abs(e.log2n - l2);
-        if (dist < best_dist) {
-            best_dist = dist;
-            best = e.parts;
-        }
-    }
-    return (best >= 1 && best_dist <= 2) ? best : 1;
+    return table_parts(n, d, g, dtype, cls);
 }
 
-GridDesc pipeline_desc(int64_t n, int d, int g, int dtype)
+GridDesc pipeline_desc(int64_t n, int d, int g, int dtype, int cls)
 {
     GridDesc gd = grid_desc(d, g);
-    const int form = refine_form(n, d, g, dtype);
+    const int form = refine_form(n, d, g, dtype, cls);
     if (form == 2 && tile_form_supported(d, g)) {
         gd.tile = 1;
         return gd;
@@ -237,7 +254,7 @@ GridDesc pipeline_desc(int64_t n, int d, int g, int dtype)
         gd.m = kWaveItemPoints;
         // items <= n, and items * parts work units must stay below 2^31
         const int64_t cap = std::max<int64_t>(1, ((int64_t)1 << 31) / std::max<int64_t>(n, 1) - 1);
-        gd.parts = (int32_t)std::min<int64_t>(wave_parts(n, d, g, dtype), cap);
+        gd.parts = (int32_t)std::min<int64_t>(wave_parts(n, d, g, dtype, cls), cap);
     }
     return gd;
 }
@@ -355,9 +372,9 @@ int validate(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t gr
     return SKYCELL_OK;
 }
 
-int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out)
+int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out, int cls)
 {
-    const int g = grid_res > 0 ? grid_res : choose_grid(n, d, dtype);
+    const int g = grid_res > 0 ? grid_res : choose_grid(n, d, dtype, cls);
     if (grid_cells(g, d) > kMaxCells)
         return fail(SKYCELL_E_RANGE,
                     "grid of %d columns in %d dimensions needs 2^(%d*%d) cells, over the budget of %u",
@@ -409,9 +426,9 @@ static int prof_mark(int i, hipStream_t st)
 
 int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
                  int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
-                 uint64_t *stats, hipStream_t st, const PivotArgs *piv, const TreeScratch *tree)
+                 uint64_t *stats, hipStream_t st, const PivotArgs *piv, const TreeScratch *tree, int cls)
 {
-    const GridDesc gd = pipeline_desc(n, d, g, dtype);
+    const GridDesc gd = pipeline_desc(n, d, g, dtype, cls);
     Workspace ws;
     workspace_layout(n, d, gd.cells, &ws, (char *)workspace);
     int dev = 0;
@@ -463,14 +480,51 @@ static int tree_scratch_for(int d, int g, int dev, hipStream_t st, TreeScratch *
     return SKYCELL_OK;
 }
 
+// Input class of n points (SKYCELL_CLASS_*): a sample's moments on `st`, read
+// back with one synchronisation of `st`.  -1 while `st` is being captured.
+static int input_class_sync(const void *points, int32_t dtype, int64_t n, int32_t d, hipStream_t st, int *cls)
+{
+    *cls = -1;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    SKYCELL_HIP_CHECK(hipStreamIsCapturing(st, &cap));
+    if (cap != hipStreamCaptureStatusNone) return SKYCELL_OK;
+    int dev = 0;
+    SKYCELL_HIP_CHECK(hipGetDevice(&dev));
+    const size_t bytes = class_moments_bytes(d);
+    void *dbuf = nullptr;
+    int rc = cached_buffer(kCacheClass, dev, st, bytes, &dbuf);
+    if (rc != SKYCELL_OK) return rc;
+    static std::mutex mu;
+    static double *host = nullptr;  // pinned, for the largest d, kept for the process
+    std::lock_guard<std::mutex> lk(mu);
+    if (host == nullptr) {
+        void *h = nullptr;
+        SKYCELL_HIP_CHECK(hipHostMalloc(&h, class_moments_bytes(SKYCELL_MAX_D), hipHostMallocDefault));
+        host = (double *)h;
+    }
+    SKYCELL_HIP_CHECK(launch_class_moments(points, dtype, n, d, (double *)dbuf, st));
+    SKYCELL_HIP_CHECK(hipMemcpyAsync(host, dbuf, bytes, hipMemcpyDeviceToHost, st));
+    SKYCELL_HIP_CHECK(hipStreamSynchronize(st));
+    *cls = class_from_moments(host, d, n);
+    return SKYCELL_OK;
+}
+
+// Inputs below this size are not classified: the read-back would cost more
+// than a differently tuned grid can save.
+constexpr int64_t kClassMinPoints = 1 << 16;
+
 static int compute_owned(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res,
                          int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *stream)
 {
     int rc = validate(points, dtype, n, d, grid_res, value_bits, out_idx, out_count);
     if (rc != SKYCELL_OK) return rc;
-    int g = 0;
-    if ((rc = resolve_grid(n, d, dtype, grid_res, &g)) != SKYCELL_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
+    int cls = -1;
+    if (grid_res == 0 && n >= kClassMinPoints && has_class_rows(n, d, dtype) &&
+        (rc = input_class_sync(points, dtype, n, d, st, &cls)) != SKYCELL_OK)
+        return rc;
+    int g = 0;
+    if ((rc = resolve_grid(n, d, dtype, grid_res, &g, cls)) != SKYCELL_OK) return rc;
     if (n == 0) {
         SKYCELL_HIP_CHECK(launch_write_zero_count(out_count, st));
         return ok();
@@ -484,7 +538,7 @@ static int compute_owned(const void *points, int32_t dtype, int64_t n, int32_t d
     bool use_tree = false;
     if ((rc = tree_scratch_for(d, g, dev, st, &ts, &use_tree)) != SKYCELL_OK) return rc;
     return run_pipeline(points, dtype, n, d, g, value_bits, out_idx, out_count, ptr, nullptr, st, nullptr,
-                        use_tree ? &ts : nullptr);
+                        use_tree ? &ts : nullptr, cls);
 }
 
 }  // namespace skycell
@@ -560,6 +614,38 @@ int skycell_choose_grid(int64_t n, int32_t d, int32_t dtype, int32_t *grid_res)
     return ok();
 }
 
+int skycell_input_class(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t *cls, void *stream)
+{
+    if (points == nullptr || cls == nullptr) return fail(SKYCELL_E_INVAL, "points and cls must not be NULL");
+    if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16)
+        return fail(SKYCELL_E_INVAL, "dtype %d is not SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16", dtype);
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(SKYCELL_E_INVAL, "n = %lld out of range", (long long)n);
+    if (d < 1 || d > SKYCELL_MAX_D) return fail(SKYCELL_E_INVAL, "d = %d is outside [1, %d]", d, SKYCELL_MAX_D);
+    int c = -1;
+    const int rc = input_class_sync(points, dtype, n, d, (hipStream_t)stream, &c);
+    if (rc != SKYCELL_OK) return rc;
+    if (c < 0) return fail(SKYCELL_E_INVAL, "the stream is being captured into a graph");
+    *cls = c;
+    return ok();
+}
+
+int skycell_choose_config(int64_t n, int32_t d, int32_t dtype, int32_t cls, int32_t *grid_res, int32_t *form,
+                          int32_t *parts)
+{
+    if (grid_res == nullptr || form == nullptr || parts == nullptr)
+        return fail(SKYCELL_E_INVAL, "grid_res, form and parts must not be NULL");
+    if (dtype != SKYCELL_DTYPE_F32 && dtype != SKYCELL_DTYPE_U16)
+        return fail(SKYCELL_E_INVAL, "dtype %d is not SKYCELL_DTYPE_F32 or SKYCELL_DTYPE_U16", dtype);
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SKYCELL_E_INVAL, "n = %lld out of range", (long long)n);
+    if (d < 1 || d > SKYCELL_MAX_D) return fail(SKYCELL_E_INVAL, "d = %d is outside [1, %d]", d, SKYCELL_MAX_D);
+    if (cls < -1 || cls > SKYCELL_CLASS_ANTICORRELATED) return fail(SKYCELL_E_INVAL, "cls = %d is not -1, 0, 1 or 2", cls);
+    const int g = choose_grid(n, d, dtype, cls);
+    *grid_res = g;
+    *form = table_form(n, d, g, dtype, cls);
+    *parts = *form == 1 ? table_parts(n, d, g, dtype, cls) : 0;
+    return ok();
+}
+
 int skycell_set_refine_form(int32_t form)
 {
     if (form < -1 || form > 3) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0, 1, 2 or 3", form);
@@ -601,10 +687,13 @@ int skycell_load_tuning(const char *path)
             TuneEntry e;
             e.form = -1;
             e.parts = 0;
-            const int got = sscanf(line, "%d %d %d %d %d %d", &e.d, &e.log2n, &e.dtype, &e.g, &e.form, &e.parts);
+            e.cls = -1;
+            const int got = sscanf(line, "%d %d %d %d %d %d %d", &e.d, &e.log2n, &e.dtype, &e.g, &e.form, &e.parts,
+                                   &e.cls);
             if (got >= 4 && e.d >= 1 && e.d <= SKYCELL_MAX_D && e.g >= 1) {
                 if (got < 5 || (e.form != 0 && e.form != 1)) e.form = -1;
                 if (got < 6 || e.parts < 1 || e.parts > kMaxWaveParts) e.parts = 0;
+                if (got < 7 || e.cls < 0 || e.cls > SKYCELL_CLASS_ANTICORRELATED) e.cls = -1;
                 entries.push_back(e);
             }
         }

@@ -27,8 +27,9 @@ int set_error(int code, const char *fmt, ...);  // records the thread's error te
 int clear_error();                               // clears it, returns SKYCELL_OK
 uint64_t grid_cells(int g, int d);               // 2^(r*d), saturated above the cell budget
 GridDesc grid_desc(int d, int g);
-// grid_desc with the refine form chosen for an instance of n points
-GridDesc pipeline_desc(int64_t n, int d, int g, int dtype);
+// grid_desc with the refine form chosen for an instance of n points (from the
+// tuning table's rows for input class cls first, when cls >= 0)
+GridDesc pipeline_desc(int64_t n, int d, int g, int dtype, int cls = -1);
 int choose_grid_batched(int64_t n, int d, int dtype);
 int device_cus(int dev);
 // Enqueue the whole single-instance path (n > 0) on `st` with a workspace of
@@ -39,14 +40,19 @@ int device_cus(int dev);
 // the prefix-OR prune's.
 int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g, int32_t value_bits,
                  int32_t *out_idx, int32_t *out_count, void *workspace, uint64_t *stats, hipStream_t st,
-                 const PivotArgs *piv = nullptr, const TreeScratch *tree = nullptr);
+                 const PivotArgs *piv = nullptr, const TreeScratch *tree = nullptr, int cls = -1);
+// Input class of the points (SKYCELL_CLASS_*) from a sample's moments
+// (input_class.hip): the launch, its buffer size, and the host-side decision.
+size_t class_moments_bytes(int d);
+hipError_t launch_class_moments(const void *pts, int dtype, int64_t n, int d, double *out, hipStream_t st);
+int class_from_moments(const double *part, int d, int64_t n);
 int validate(const void *points, int32_t dtype, int64_t n, int32_t d, int32_t grid_res, int32_t value_bits,
              const int32_t *out_idx, const int32_t *out_count);
-int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out);
+int resolve_grid(int64_t n, int32_t d, int32_t dtype, int32_t grid_res, int *g_out, int cls = -1);
 size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *base);
 // Library-owned device buffer per (slot, device, stream), grown on demand
 // (the stream is synchronised before an old buffer is freed).
-enum CacheSlot { kCacheWorkspace = 0, kCachePivots = 1, kCacheTree = 2, kCacheFine = 3, kCacheCount = 4 };
+enum CacheSlot { kCacheWorkspace = 0, kCachePivots = 1, kCacheTree = 2, kCacheFine = 3, kCacheClass = 4, kCacheCount = 5 };
 
 // Scratch of the paper's tree-form cell prune (Algorithm 3 per layer) for
 // grids of cells = 2^(rho*d) cells.

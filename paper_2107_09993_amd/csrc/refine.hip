@@ -43,125 +43,6 @@ struct XcdFeeder {
     }
 };
 
-// Walk records (common.h) of every cell, after the scatter: the record's
-// lower-neighbour mask and the bytewise minimum of the screening columns of the
-// cell's sorted points, halved into 6-bit fields.  One lane per cell; a cell
-// with more than kWrecLanePoints points is reduced by the whole wave together
-// (strided loads, then a butterfly of bytewise minima).  Every lane of the
-// launch stays active to the end (lanes past the last cell hold no points), so
-// the butterfly sees all 64 lanes.
-constexpr uint32_t kWrecLanePoints = 32;
-
-// Bytewise minimum of two words of 7-bit bytes.
-__device__ __forceinline__ uint64_t bytes_min(uint64_t a, uint64_t b)
-{
-    const uint64_t ge = ((b | kHigh) - a) & kHigh;  // top bit of a byte: b >= a there
-    const uint64_t sel = (ge - (ge >> 7)) | ge;     // 0xFF in those bytes
-    return (a & sel) | (b & ~sel);
-}
-
-template <int D>
-__global__ __launch_bounds__(kRefineThreads) void k_wrec(const uint64_t *__restrict__ rec,
-                                                         const uint64_t *__restrict__ fkeys,
-                                                         uint64_t *__restrict__ wrec, uint32_t cells)
-{
-    constexpr uint32_t kAll = (1u << D) - 1u;
-    constexpr uint64_t kNone = 0x7F7F7F7F7F7F7F7Full;
-    const uint32_t x = blockIdx.x * kRefineThreads + threadIdx.x;
-    const bool mine = x < cells;
-    const uint64_t r = mine ? rec[x] : 0ull;
-    uint32_t s = 0u, c = 0u;
-    if (rec_surv(r)) {
-        s = rec_start(r);
-        c = rec_count(r);
-        if (c == kRecCountSat) c = rec_start(rec[x + 1]) - s;
-    }
-    uint64_t mn = kNone;
-    const uint32_t own = c <= kWrecLanePoints ? c : 0u;
-    for (uint32_t i = 0; i < own; ++i) mn = bytes_min(mn, fkeys[s + i]);
-    uint64_t big = __ballot(c > kWrecLanePoints);
-    while (big != 0ull) {
-        const int l = __builtin_ctzll(big);
-        big &= big - 1ull;
-        const uint32_t bs = __builtin_amdgcn_readlane(s, l);
-        const uint32_t bc = __builtin_amdgcn_readlane(c, l);
-        uint64_t part = kNone;
-        for (uint32_t i = __lane_id(); i < bc; i += kWave) part = bytes_min(part, fkeys[bs + i]);
-        for (int off = kWave / 2; off > 0; off >>= 1) part = bytes_min(part, __shfl_xor(part, off));
-        if (__lane_id() == (unsigned)l) mn = part;
-    }
-    if (!mine) return;
-    uint64_t wv = 0ull;
-#pragma unroll
-    for (int k = 0; k < D; ++k) wv |= ((mn >> (8 * k + 1)) & 0x3Full) << (7 * k);
-    reinterpret_cast<ulonglong2 *>(wrec)[x] = make_ulonglong2(wv | ((uint64_t)(rec_nbr(r) & kAll) << 56), wv);
-}
-
-// Fieldwise minimum of two words of 6-bit fields in 7-bit slots (guard bits zero).
-__device__ __forceinline__ uint64_t fields_min(uint64_t a, uint64_t b)
-{
-    constexpr uint64_t kG = wrec_guards();
-    const uint64_t ge = ((b | kG) - a) & kG;  // guard bit of a field: b >= a there
-    const uint64_t sel = (ge - (ge >> 6)) | ge;
-    return (a & sel) | (b & ~sel);
-}
-
-// Prefix minimum of the walk records' first words over the first P dimensions
-// (word 2x, common.h).  One workgroup per tile: the 2^(P*r) cells that share the
-// index bits outside the P dimensions; tile element t has bit b*P + k for index
-// bit b*D + k.  Per dimension k and column bit b, in increasing b, every element
-// with that bit set takes the minimum with the element that has it cleared and
-// dimension k's lower column bits all set: afterwards each element holds the
-// minimum over the elements <= it in those dimensions.
-template <int D>
-__global__ __launch_bounds__(kRefineThreads) void k_wrec_prefix(uint64_t *__restrict__ wrec, int r, int pdims,
-                                                                uint32_t cells)
-{
-    __shared__ uint64_t s_v[1u << kWrecTileBits];
-    __shared__ uint8_t s_nb[1u << kWrecTileBits];
-    const int tb = pdims * r;
-    const uint32_t tsize = 1u << tb;
-    uint32_t inmask = 0u;
-    for (int b = 0; b < r; ++b)
-        for (int k = 0; k < pdims; ++k) inmask |= 1u << (b * D + k);
-    // the tile number's bits, in order, at the index bits outside the tile
-    const uint32_t outmask = (cells - 1u) & ~inmask;
-    uint32_t base = 0u, tile = blockIdx.x;
-    for (int p = 0; p < 32 && tile != 0u; ++p) {
-        if ((outmask >> p) & 1u) {
-            base |= (tile & 1u) << p;
-            tile >>= 1;
-        }
-    }
-    const uint32_t lowdims = (1u << pdims) - 1u;
-    auto cell_of = [&](uint32_t t) {
-        uint32_t xi = base;
-        for (int b = 0; b < r; ++b) xi |= ((t >> (b * pdims)) & lowdims) << (b * D);
-        return xi;
-    };
-    for (uint32_t t = threadIdx.x; t < tsize; t += kRefineThreads) {
-        const uint64_t w = wrec[2 * (size_t)cell_of(t)];
-        s_v[t] = w & kWrecFields;
-        s_nb[t] = (uint8_t)(w >> 56);
-    }
-    __syncthreads();
-    for (int k = 0; k < pdims; ++k) {
-        uint32_t low = 0u;
-        for (int b = 0; b < r; ++b) {
-            const int pos = b * pdims + k;
-            const uint32_t pbit = 1u << pos;
-            for (uint32_t u = threadIdx.x; u < tsize / 2; u += kRefineThreads) {
-                const uint32_t t = ((u >> pos) << (pos + 1)) | pbit | (u & (pbit - 1u));
-                s_v[t] = fields_min(s_v[t], s_v[(t & ~pbit) | low]);
-            }
-            __syncthreads();
-            low |= pbit;
-        }
-    }
-    for (uint32_t t = threadIdx.x; t < tsize; t += kRefineThreads)
-        wrec[2 * (size_t)cell_of(t)] = s_v[t] | ((uint64_t)s_nb[t] << 56);
-}
-
 template <int D, int M, bool MC>
 __global__ __launch_bounds__(kRefineThreads) void k_refine(const uint32_t *__restrict__ keys,
                                                            const uint64_t *__restrict__ fkeys,
@@ -252,10 +133,6 @@ static unsigned refine_blocks(int64_t n, int num_cus)
     return (unsigned)(need < full ? need : full);
 }
 
-// The lane form with walk records (d <= kWrecMaxD unless the plain lane form
-// was asked for).
-inline bool lane_mc(const GridDesc &gd) { return gd.d <= kWrecMaxD && gd.plain == 0; }
-
 template <int D, int M>
 static hipError_t launch_refine_dm(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                                    int num_cus, hipStream_t st)
@@ -316,37 +193,6 @@ static hipError_t prepare_d(const GridDesc &gd)
     case 4:
         prepare_dm<D, 4>(gd);
         return hipSuccess;
-    default:
-        return hipErrorInvalidValue;
-    }
-}
-
-// Walk records for the lane form's minimum-corner screen (after the scatter;
-// nothing to do for the other forms).
-hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, hipStream_t st)
-{
-    if (gd.tile || gd.m == kWaveItemPoints || !lane_mc(gd)) return hipSuccess;
-    const unsigned wb = (gd.cells + kRefineThreads - 1) / kRefineThreads;
-    const int pdims = wrec_prefix_dims(gd.d, gd.r);
-    const unsigned tiles = pdims > 0 ? gd.cells >> (pdims * gd.r) : 0u;
-    switch (gd.d) {
-#define SKYCELL_WREC_CASE(DD)                                                                              \
-    case DD:                                                                                               \
-        hipLaunchKernelGGL((k_wrec<DD>), dim3(wb), dim3(kRefineThreads), 0, st, (const uint64_t *)ws.rec,    \
-                           (const uint64_t *)ws.fkeys, ws.wrec, gd.cells);                                  \
-        if (tiles > 0)                                                                                     \
-            hipLaunchKernelGGL((k_wrec_prefix<DD>), dim3(tiles), dim3(kRefineThreads), 0, st, ws.wrec, gd.r, \
-                               pdims, gd.cells);                                                           \
-        return hipGetLastError();
-        SKYCELL_WREC_CASE(1)
-        SKYCELL_WREC_CASE(2)
-        SKYCELL_WREC_CASE(3)
-        SKYCELL_WREC_CASE(4)
-        SKYCELL_WREC_CASE(5)
-        SKYCELL_WREC_CASE(6)
-        SKYCELL_WREC_CASE(7)
-        SKYCELL_WREC_CASE(8)
-#undef SKYCELL_WREC_CASE
     default:
         return hipErrorInvalidValue;
     }

@@ -132,6 +132,37 @@ def test_tuning_table_roundtrip(tmp_path):
         sky.load_tuning(shipped if os.path.exists(shipped) else None)
 
 
+def test_class_rows_of_the_tuning_table(tmp_path):
+    """Rows tuned on one input class win for that class; other classes fall
+    back to the rows chosen over all classes."""
+    shipped = os.path.join(os.path.dirname(sky.__file__), "tuning", "mi355x.txt")
+    p = tmp_path / "classes.txt"
+    p.write_text("# d log2n dtype g form parts class\n8 20 0 3 1 16\n8 20 0 8 1 12 1\n8 20 0 6 0 1 2\n"
+                 "8 20 0 5 1 4 7\n")
+    try:
+        sky.load_tuning(str(p))
+        assert sky.choose_config(1_000_000, 8) == (3, "wave", 16)
+        assert sky.choose_config(1_000_000, 8, cls=sky.CLASS_INDEPENDENT) == (3, "wave", 16)
+        assert sky.choose_config(1_000_000, 8, cls=sky.CLASS_CORRELATED) == (8, "wave", 12)
+        assert sky.choose_config(1_000_000, 8, cls=sky.CLASS_ANTICORRELATED) == (6, "lane", 0)
+        # a class outside 0..2 in the table is read as "any class": the 7-class
+        # line then competes with the first any-class line at the same distance
+        assert sky.choose_grid(1_000_000, 8) in (3, 5)
+        # rows more than a factor ~2 away in n do not apply to the grid choice
+        assert sky.choose_config(1 << 24, 8, cls=sky.CLASS_CORRELATED)[0] == sky.choose_grid(1 << 24, 8)
+        lib = sky.lib()
+        g, f, q = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert lib.skycell_choose_config(10, 8, 0, 3, ctypes.byref(g), ctypes.byref(f), ctypes.byref(q)) == sky.E_INVAL
+        assert lib.skycell_choose_config(10, 8, 0, -1, None, ctypes.byref(f), ctypes.byref(q)) == sky.E_INVAL
+        c = ctypes.c_int32()
+        assert lib.skycell_input_class(None, 0, 10, 8, ctypes.byref(c), None) == sky.E_INVAL
+        assert lib.skycell_input_class(FAKE, 0, 0, 8, ctypes.byref(c), None) == sky.E_INVAL
+        assert lib.skycell_input_class(FAKE, 0, 10, 17, ctypes.byref(c), None) == sky.E_INVAL
+        assert lib.skycell_input_class(FAKE, 5, 10, 8, ctypes.byref(c), None) == sky.E_INVAL
+    finally:
+        sky.load_tuning(shipped if os.path.exists(shipped) else None)
+
+
 def test_wave_parts_argument_errors():
     for bad in (-1, 65):
         with pytest.raises(sky.SkycellError) as e:

@@ -101,6 +101,38 @@ def test_single_workload_other_grids(inputs, name, grid):
     assert_golden(x, run_plain(x, grid_res=grid), e, "%s at g = %d" % (name, grid))
 
 
+@pytest.mark.parametrize("name,cls", [("C2-ind", 0), ("C2-corr", 1), ("C2-anti", 2)])
+def test_c2_class_tuned_configurations(inputs, name, cls):
+    """The library classifies each C2 input, and the configuration tuned for
+    that class (through the Python binding, and through skycell_compute with
+    grid_res = 0, which classifies the input itself) gives the oracle's
+    skyline."""
+    import ctypes
+    e = GOLDEN["single"][name]
+    x = inputs(name)
+    dev = _dev()
+    n, d = x.shape
+    soa = torch.from_numpy(np.ascontiguousarray(x.T)).to(dev)
+    assert sky.input_class(soa) == cls
+    g, form, parts = sky.choose_config(n, d, sky.DTYPE_F32, cls)
+    sky.set_refine_form(form)
+    sky.set_wave_parts(parts if form == "wave" else 0)
+    try:
+        got = run_plain(x, grid_res=g)
+    finally:
+        sky.set_refine_form("auto")
+        sky.set_wave_parts(0)
+    assert_golden(x, got, e, "%s with its class configuration g = %d, %s" % (name, g, form))
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    rc = sky.lib().skycell_compute(ctypes.c_void_p(soa.data_ptr()), n, d, 0, ctypes.c_void_p(idx.data_ptr()),
+                                   ctypes.c_void_p(cnt.data_ptr()), st)
+    assert rc == sky.OK
+    c = int(cnt.item())
+    assert_golden(x, idx[:c].cpu().numpy(), e, "%s through skycell_compute" % name)
+
+
 @pytest.mark.parametrize("form", ["lane", "wave"])
 def test_c2_anti_both_refine_forms(inputs, form):
     e = GOLDEN["single"]["C2-anti"]

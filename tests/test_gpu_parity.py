@@ -73,6 +73,15 @@ def test_grid_resolution_invariance(oracle_mod, g):
     check(x, oracle_mod, grid_res=g)
 
 
+@pytest.mark.parametrize("d,g", [(1, 1 << 20), (2, 4096), (2, 3000), (3, 256)])
+def test_fine_grids_at_low_d(oracle_mod, d, g):
+    """Grids whose column bits above the 64-cell bitmap word exceed one tile of
+    the lower-closure pass (d <= 2), and the largest d = 3 grid."""
+    for dist in ("independent", "anticorrelated"):
+        x = datagen.generate(dist, 40_000, d, seed=17 + d)
+        check(x, oracle_mod, grid_res=g)
+
+
 @pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
 @pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 10, 12, 16])
 def test_distributions_and_dims(oracle_mod, dist, d):
