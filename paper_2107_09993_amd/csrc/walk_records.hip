@@ -27,6 +27,8 @@ constexpr int kWrecThreads = 256;
 //      the record's lower-neighbour mask: the first word.
 constexpr uint32_t kWrecLanePoints = 32;
 constexpr int kWrecBatch = 4;
+constexpr int kWrecRounds = (1 << kWrecTileBits) / (kWrecThreads * kWrecBatch);
+static_assert(kWrecRounds * kWrecThreads * kWrecBatch == (1 << kWrecTileBits), "rounds cover a whole tile");
 
 // Bytewise minimum of two words of 7-bit bytes.
 __device__ __forceinline__ uint64_t bytes_min(uint64_t a, uint64_t b)
@@ -82,10 +84,15 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
     // 1. own minima, kWrecBatch cells per thread and round so that their record
     // and first screening-word loads are in flight together; every lane runs
     // every round (lanes past the tile hold no points), so the butterfly of a
-    // large cell sees all 64 lanes
-    for (uint32_t t0 = 0; t0 < tsize; t0 += kWrecThreads * kWrecBatch) {
+    // large cell sees all 64 lanes.  The minima stay in registers until both
+    // words of a record are written together.
+    uint64_t own[kWrecRounds][kWrecBatch];
+#pragma unroll
+    for (int rd = 0; rd < kWrecRounds; ++rd) {
+        const uint32_t t0 = (uint32_t)rd * kWrecThreads * kWrecBatch;
+        if (t0 >= tsize) break;
         uint32_t xi[kWrecBatch], s[kWrecBatch], c[kWrecBatch];
-        uint64_t rr[kWrecBatch], mn[kWrecBatch];
+        uint64_t rr[kWrecBatch];
 #pragma unroll
         for (int q = 0; q < kWrecBatch; ++q) {
             const uint32_t t = t0 + (uint32_t)q * kWrecThreads + threadIdx.x;
@@ -102,6 +109,7 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
                 if (c[q] == kRecCountSat) c[q] = rec_start(rec[xi[q] + 1]) - s[q];
             }
         }
+        uint64_t mn[kWrecBatch];
 #pragma unroll
         for (int q = 0; q < kWrecBatch; ++q) {
             const bool small = c[q] <= kWrecLanePoints;
@@ -111,8 +119,8 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
         }
 #pragma unroll
         for (int q = 0; q < kWrecBatch; ++q) {
-            const uint32_t own = c[q] <= kWrecLanePoints ? c[q] : 0u;
-            for (uint32_t i = 2; i < own; ++i) mn[q] = bytes_min(mn[q], fkeys[s[q] + i]);
+            const uint32_t cnt_own = c[q] <= kWrecLanePoints ? c[q] : 0u;
+            for (uint32_t i = 2; i < cnt_own; ++i) mn[q] = bytes_min(mn[q], fkeys[s[q] + i]);
             uint64_t big = __ballot(c[q] > kWrecLanePoints);
             while (big != 0ull) {
                 const int l = __builtin_ctzll(big);
@@ -124,12 +132,12 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
                 for (int off = kWave / 2; off > 0; off >>= 1) part = bytes_min(part, __shfl_xor(part, off));
                 if (__lane_id() == (unsigned)l) mn[q] = part;
             }
+            uint64_t wv = 0ull;
+#pragma unroll
+            for (int k = 0; k < D; ++k) wv |= ((mn[q] >> (8 * k + 1)) & 0x3Full) << (7 * k);
+            own[rd][q] = wv;
             const uint32_t t = t0 + (uint32_t)q * kWrecThreads + threadIdx.x;
             if (t < tsize) {
-                uint64_t wv = 0ull;
-#pragma unroll
-                for (int k = 0; k < D; ++k) wv |= ((mn[q] >> (8 * k + 1)) & 0x3Full) << (7 * k);
-                wrec[2 * (size_t)xi[q] + 1] = wv;
                 s_v[t] = wv;
                 s_nb[t] = (uint8_t)(rec_nbr(rr[q]) & kAll);
             }
@@ -150,8 +158,16 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
             low |= pbit;
         }
     }
-    for (uint32_t t = threadIdx.x; t < tsize; t += kWrecThreads)
-        wrec[2 * (size_t)cell_of(t)] = s_v[t] | ((uint64_t)s_nb[t] << 56);
+#pragma unroll
+    for (int rd = 0; rd < kWrecRounds; ++rd) {
+#pragma unroll
+        for (int q = 0; q < kWrecBatch; ++q) {
+            const uint32_t t = (uint32_t)rd * kWrecThreads * kWrecBatch + (uint32_t)q * kWrecThreads + threadIdx.x;
+            if (t < tsize)
+                reinterpret_cast<ulonglong2 *>(wrec)[cell_of(t)] =
+                    make_ulonglong2(s_v[t] | ((uint64_t)s_nb[t] << 56), own[rd][q]);
+        }
+    }
 }
 
 // Walk records for the lane form's minimum-corner screen (after the scatter;
