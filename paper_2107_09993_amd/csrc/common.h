@@ -190,6 +190,11 @@ hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc 
                           const Workspace &ws, int value_bits, int num_cus, hipStream_t st);
 // The lane form of the refine reads walk records (d <= kWrecMaxD unless the
 // plain lane form was asked for).
+// The walk-record loop addresses its arrays with 32-bit buffer offsets (items
+// and screening words take 8 bytes per point), so larger inputs get the plain
+// lane form (pipeline_desc sets gd.plain).
+constexpr int64_t kWrecMaxPoints = (int64_t)1 << 28;
+static_assert((kMaxD & (kMaxD - 1)) == 0, "the walk's shared tables are indexed modulo kMaxD");
 inline bool lane_mc(const GridDesc &gd) { return gd.d <= kWrecMaxD && gd.plain == 0; }
 // Walk records of the lane form (walk_records.hip), built from the sorted
 // points; launch_scatter ends with it.

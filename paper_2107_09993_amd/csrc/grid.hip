@@ -233,26 +233,43 @@ __global__ __launch_bounds__(kThreads) void k_lc_step(uint64_t *__restrict__ lcb
 }
 
 // Per cell: the high half of the cell record (see cellops.h); the scan fills
-// in the low half (first sorted position).
+// in the low half (first sorted position).  Grid-stride over the cells, so that
+// with statistics on, each workgroup adds its totals with one atomic per
+// counter at the end (one atomic per wave on the same two words serialised).
+constexpr uint32_t kCellRecBlocks = 2048;
+
 __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32_t *__restrict__ cnt,
                                                        const uint64_t *__restrict__ lc,
                                                        uint64_t *__restrict__ rec,
                                                        uint64_t *__restrict__ survbits,
                                                        uint64_t *__restrict__ stats)
 {
-    const uint32_t x = blockIdx.x * kThreads + threadIdx.x;
-    bool occ = false, surv = false;
-    if (x < gd.cells) rec[x] = cell_record(gd, cnt, lc, x, occ, surv);
-    // one bitmap word per wave: the wave's 64 cells start at a multiple of 64
-    const uint64_t bs = __ballot(surv);
-    if (__lane_id() == 0 && x < gd.cells) survbits[x >> 6] = bs;
+    uint32_t nocc = 0u, nsurv = 0u;  // wave-uniform running totals
+    for (uint32_t base = blockIdx.x * kThreads; base < gd.cells; base += gridDim.x * kThreads) {
+        const uint32_t x = base + threadIdx.x;
+        bool occ = false, surv = false;
+        if (x < gd.cells) rec[x] = cell_record(gd, cnt, lc, x, occ, surv);
+        // one bitmap word per wave: the wave's 64 cells start at a multiple of 64
+        const uint64_t bs = __ballot(surv);
+        if (__lane_id() == 0 && x < gd.cells) survbits[x >> 6] = bs;
+        nocc += (uint32_t)__popcll(__ballot(occ));
+        nsurv += (uint32_t)__popcll(bs);
+    }
     if (stats != nullptr) {
-        const uint64_t bo = __ballot(occ);
+        __shared__ uint32_t s_occ[kThreads / kWave], s_surv[kThreads / kWave];
         if (__lane_id() == 0) {
-            if (bo) atomicAdd((unsigned long long *)&stats[SKYCELL_STAT_NONEMPTY_CELLS],
-                              (unsigned long long)__popcll(bo));
-            if (bs) atomicAdd((unsigned long long *)&stats[SKYCELL_STAT_SURVIVING_CELLS],
-                              (unsigned long long)__popcll(bs));
+            s_occ[threadIdx.x / kWave] = nocc;
+            s_surv[threadIdx.x / kWave] = nsurv;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t o = 0ull, v = 0ull;
+            for (int w = 0; w < kThreads / kWave; ++w) {
+                o += s_occ[w];
+                v += s_surv[w];
+            }
+            if (o) atomicAdd((unsigned long long *)&stats[SKYCELL_STAT_NONEMPTY_CELLS], (unsigned long long)o);
+            if (v) atomicAdd((unsigned long long *)&stats[SKYCELL_STAT_SURVIVING_CELLS], (unsigned long long)v);
         }
     }
 }
@@ -273,7 +290,9 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *
             }
         }
     }
-    hipLaunchKernelGGL(k_cell_rec, grid_for(gd.cells), dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
+    dim3 rgrid = grid_for(gd.cells);
+    if (rgrid.x > kCellRecBlocks) rgrid.x = kCellRecBlocks;
+    hipLaunchKernelGGL(k_cell_rec, rgrid, dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
                        ws.rec, ws.survbits, stats);
     return hipGetLastError();
 }

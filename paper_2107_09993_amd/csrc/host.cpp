@@ -249,7 +249,7 @@ GridDesc pipeline_desc(int64_t n, int d, int g, int dtype, int cls)
         gd.tile = 1;
         return gd;
     }
-    if (form == 3) gd.plain = 1;
+    if (form == 3 || n >= kWrecMaxPoints) gd.plain = 1;
     if (form == 1) {
         gd.m = kWaveItemPoints;
         // items <= n, and items * parts work units must stay below 2^31

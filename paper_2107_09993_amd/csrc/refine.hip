@@ -4,7 +4,10 @@
 // share b % kNumXcd (the XCD it is dispatched to), so the waves sharing an L2
 // work on neighbouring cells and their cones, and moves on to the other shares
 // once its own is empty.  A wave takes `chunk` items per atomic: small chunks
-// keep the waves of an XCD on a narrow front of neighbouring cells.
+// keep the waves of an XCD on a narrow front of neighbouring cells, but every
+// request is a device-scope atomic on one of eight queue heads; 64 items per
+// request measured best (8 items per request made the headline refine 1.8x
+// slower, 256 about 8% slower).
 #include <cstdlib>
 
 #include "common.h"
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const uint32_t *__res
                                                            const uint2 *__restrict__ items,
                                                            uint32_t *__restrict__ ctr,
                                                            uint8_t *__restrict__ flag, GridDesc gd,
-                                                           uint32_t chunk, uint64_t *__restrict__ stats)
+                                                           uint32_t chunk, uint32_t n, uint64_t *__restrict__ stats)
 {
     __shared__ uint32_t s_mask[kMaxD], s_low[kMaxD];
     if (threadIdx.x < kMaxD) {
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const uint32_t *__res
     XcdFeeder feed{ctr + kCtrHead, ctr[kCtrItems], chunk, (int)(blockIdx.x % kNumXcd), kNumXcd};
     uint32_t visits = 0u, tests = 0u;
     if constexpr (MC)
-        refine_loop_mc<D, M>(v, wrec, wrec_prefix_dims(D, gd.r), feed, visits, tests);
+        refine_loop_mc<D, M>(v, wrec, wrec_prefix_dims(D, gd.r), n, gd.cells, feed, visits, tests);
     else
         refine_loop<D, M>(v, feed, visits, tests);
 
@@ -92,7 +95,7 @@ static uint32_t refine_chunk()
     if (chunk < 0) {
         const char *v = getenv("SKYCELL_REFINE_CHUNK");
         chunk = v ? atoi(v) : 0;
-        if (chunk < 1 || chunk > 4096) chunk = 32;
+        if (chunk < 1 || chunk > 4096) chunk = 64;
     }
     return (uint32_t)chunk;
 }
@@ -143,14 +146,14 @@ static hipError_t launch_refine_dm(int64_t n, const GridDesc &gd, const Workspac
         hipLaunchKernelGGL((k_refine<D, M, kCanMc>), dim3(blocks), dim3(kRefineThreads), 0, st,
                            (const uint32_t *)ws.keys, (const uint64_t *)ws.fkeys, (const int32_t *)ws.sidx,
                            (const uint64_t *)ws.rec, (const uint64_t *)ws.wrec, (const uint2 *)ws.items, ws.ctr,
-                           ws.flag, gd, refine_chunk(), stats);
+                           ws.flag, gd, refine_chunk(), (uint32_t)n, stats);
         return hipGetLastError();
     }
     const unsigned blocks = refine_blocks<D, M, false>(n, num_cus);
     hipLaunchKernelGGL((k_refine<D, M, false>), dim3(blocks), dim3(kRefineThreads), 0, st,
                        (const uint32_t *)ws.keys, (const uint64_t *)ws.fkeys, (const int32_t *)ws.sidx,
                        (const uint64_t *)ws.rec, (const uint64_t *)nullptr, (const uint2 *)ws.items, ws.ctr,
-                       ws.flag, gd, refine_chunk(), stats);
+                       ws.flag, gd, refine_chunk(), (uint32_t)n, stats);
     return hipGetLastError();
 }
 

@@ -32,9 +32,36 @@
 
 namespace skycell {
 
+// The loop's per-turn loads are raw buffer loads: a 32-bit byte offset against
+// a resource that holds the array's base and size, so no 64-bit address
+// arithmetic per load, and a lane with nothing to load passes an offset past
+// the end (kMcNoLoad), for which the hardware returns zero without touching
+// memory, instead of branching around the load.  Every array then has to stay
+// below 2^31 bytes: the host uses this loop only for n < kWrecMaxPoints
+// (2^26 cells of 16-byte walk records are 2^30 bytes).
+constexpr uint32_t kMcNoLoad = 0x80000000u;
+constexpr uint32_t kBufferWord3 = 0x00020000u;  // raw 32-bit elements, gfx9 resource format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, (int)kBufferWord3);
+}
+__device__ __forceinline__ uint64_t buffer_u64(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return ((uint64_t)v[1] << 32) | v[0];
+}
+__device__ __forceinline__ ulonglong2 buffer_u128(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_ulonglong2(((uint64_t)v[1] << 32) | v[0], ((uint64_t)v[3] << 32) | v[2]);
+}
+
+// n: points of the instance (sizes of the item and screening-word arrays),
+// cells: its index space (sizes of the cell and walk records).
 template <int D, int M, class Feeder>
-__device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__ wrec, int pdims, Feeder &feed,
-                               uint32_t &visits, uint32_t &tests)
+__device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__ wrec, int pdims, uint32_t n,
+                               uint32_t cells, Feeder &feed, uint32_t &visits, uint32_t &tests)
 {
     static_assert(D >= 1 && D <= kWrecMaxD, "walk records hold at most kWrecMaxD dimensions");
     constexpr uint32_t kAll = (1u << D) - 1u;
@@ -42,6 +69,8 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
     constexpr uint64_t kGuard = wrec_guards();
     const int lane = __lane_id();
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const __amdgpu_buffer_rsrc_t rs_items = raw_buffer(v.items, n * 8u), rs_rec = raw_buffer(v.rec, (cells + 1u) * 8u),
+                                 rs_fkeys = raw_buffer(v.fkeys, n * 8u), rs_wrec = raw_buffer(wrec, cells * 16u);
 
     uint32_t q[M][D];
     uint64_t qf[M], q6[M];
@@ -99,11 +128,10 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
         const bool can_step = active && walking && used <= 1u;
 
         // ---- issue this turn's loads
-        uint2 it = make_uint2(0u, 0u);
-        if (st == 1) it = v.items[my];
-        uint64_t r0 = 0ull;
+        const uint64_t it64 = buffer_u64(rs_items, st == 1 ? my * 8u : kMcNoLoad);
+        const uint2 it = make_uint2((uint32_t)it64, (uint32_t)(it64 >> 32));
+        const uint64_t r0 = buffer_u64(rs_rec, st == 2 ? root * 8u : kMcNoLoad);
         if (st == 2) {
-            r0 = v.rec[root];
 #pragma unroll
             for (int t = 0; t < M; ++t) {
                 const uint32_t row = qstart + ((uint32_t)t < qcnt ? (uint32_t)t : qcnt - 1u);
@@ -113,29 +141,21 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
         }
         const bool c0ok = active && cur < end;
         const bool c1ok = active && cur + 1 < end;
-        uint64_t f0 = 0ull, f1 = 0ull;
-        if (c0ok) f0 = v.fkeys[cur];
-        if (c1ok) f1 = v.fkeys[cur + 1];
+        const uint64_t f0 = buffer_u64(rs_fkeys, c0ok ? cur * 8u : kMcNoLoad);
+        const uint64_t f1 = buffer_u64(rs_fkeys, c1ok ? cur * 8u + 8u : kMcNoLoad);
         const bool exok = active && exmask != 0u;
         uint32_t e[D];
         if (exok) load_keys<D>(v.keys, ex, e);
-        uint64_t rr = 0ull;
         const bool rqok = active && rqv;
-        if (rqok) rr = v.rec[rq];
-        bool stepped = false;
-        int j = 0;
-        uint32_t y = 0u;
-        ulonglong2 w = make_ulonglong2(0ull, 0ull);
-        if (can_step) {
-            if (diag == 0u) {
-                walking = false;
-            } else {
-                j = __ffs(diag) - 1;
-                y = morton_dec((x & ~v.low[j]) | (root & v.low[j]), v.mask[j]);
-                w = reinterpret_cast<const ulonglong2 *>(wrec)[y];
-                stepped = true;
-            }
-        }
+        const uint64_t rr = buffer_u64(rs_rec, rqok ? rq * 8u : kMcNoLoad);
+        // the next cell of the walk (computed on every lane: j = -1 when diag
+        // is empty reads the last, unused entry of the shared tables)
+        if (can_step && diag == 0u) walking = false;
+        const bool stepped = can_step && diag != 0u;
+        const int j = __ffs(diag) - 1;
+        const uint32_t lowj = v.low[j & (kMaxD - 1)];
+        const uint32_t y = morton_dec((x & ~lowj) | (root & lowj), v.mask[j & (kMaxD - 1)]);
+        const ulonglong2 w = buffer_u128(rs_wrec, stepped ? y * 16u : kMcNoLoad);
 
         // ---- item setup
         if (st == 1) {
