@@ -1,6 +1,7 @@
 // K5: the exact refine of one instance over the whole GPU (the lane loop is in
 // refine_core.h).  Work items are in Morton order of their cells and split
-// into kNumXcd contiguous shares with one queue each; workgroup b starts on
+// into kNumXcd contiguous shares with one queue each (taken from the top of
+// the share down); workgroup b starts on
 // share b % kNumXcd (the XCD it is dispatched to), so the waves sharing an L2
 // work on neighbouring cells and their cones, and moves on to the other shares
 // once its own is empty.  A wave takes `chunk` items per atomic: small chunks
@@ -33,10 +34,13 @@ struct XcdFeeder {
             const uint32_t s_hi = (uint32_t)(((uint64_t)n_items * (share + 1)) / kNumXcd);
             uint32_t base = 0u;
             if (__lane_id() == 0) base = atomicAdd(&heads[share], chunk);
-            base = __shfl(base, 0) + s_lo;
-            if (base < s_hi) {
-                lo = base;
-                hi = base + chunk < s_hi ? base + chunk : s_hi;
+            base = __shfl(base, 0);
+            if (base < s_hi - s_lo) {
+                // from the top of the share down: the cells with the highest
+                // columns, whose cone walks are the longest on average, are
+                // handed out first and do not start near the end of the launch
+                hi = s_hi - base;
+                lo = hi - s_lo > chunk ? hi - chunk : s_lo;
                 return true;
             }
             share = share + 1 == kNumXcd ? 0 : share + 1;
