@@ -275,6 +275,23 @@ int skycell_set_pivot_gate(int32_t on);
 int skycell_set_cell_prune(int32_t form);
 
 /*
+ * Slab split of the lane refine for all later calls in the process (d <= 8,
+ * lane form with minimum corners): the cells with the largest cone-size
+ * estimate prod_k (c_k + 1), about 1/512 of the work items, get one work item
+ * per slab of their lower cone (the cells with one column of dimension d-1,
+ * walked in dimensions 0..d-2), so that the longest cone walks run in
+ * parallel on neighbouring lanes instead of holding one lane, and the launch,
+ * past the others (Algorithm 1's RefineSkyline; the split changes only how
+ * the cone of a cell is divided among lanes).  -1 = on from d = 7 and 2^18
+ * points (measured faster there, slower on small calls), 0 = off, 1 = on
+ * whenever the form allows it, 2 = as many cells, largest estimate first, as
+ * the workspace's n work item slots have room for (for tests).  A split that
+ * would need more than those slots is not made.  The result never depends on
+ * it.  Returns SKYCELL_E_INVAL unless mode is -1, 0, 1 or 2.
+ */
+int skycell_set_slab_split(int32_t mode);
+
+/*
  * The tree form's layers on their own, for tests and measurements: the points'
  * occupancy at g = 2^rho (1 <= rho, rho * d <= 26; Equation 1 per layer), then
  * Algorithm 3 for layers 1..rho.  key_out and cand_out (device uint64 bitmaps)

@@ -62,6 +62,7 @@ def lib():
                                         ctypes.POINTER(i32)]
     L.skycell_load_tuning.argtypes = [ctypes.c_char_p]
     L.skycell_set_refine_form.argtypes = [i32]
+    L.skycell_set_slab_split.argtypes = [i32]
     L.skycell_set_wave_parts.argtypes = [i32]
     L.skycell_set_pivot_gate.argtypes = [i32]
     L.skycell_set_cell_prune.argtypes = [i32]
@@ -107,6 +108,7 @@ def lib():
                  "skycell_compute_ws", "skycell_compute_static", "skycell_choose_grid", "skycell_load_tuning", "skycell_set_refine_form",
                  "skycell_input_class", "skycell_choose_config",
                  "skycell_set_wave_parts", "skycell_set_pivot_gate", "skycell_set_cell_prune",
+                 "skycell_set_slab_split",
                  "skycell_shrink_tree", "skycell_compute_layered",
                  "skycell_workspace_layout", "skycell_profile_enable", "skycell_profile_read",
                  "skycell_batched_plan_create", "skycell_batched_offsets", "skycell_batched_run",
@@ -215,6 +217,16 @@ def set_pivot_gate(on):
     skips the full pass when a sample shows almost nothing to remove; False
     always screens every point of a surviving cell against the pivots."""
     _check(lib().skycell_set_pivot_gate(1 if on else 0))
+
+
+SLAB_SPLIT_MODES = {"auto": -1, "off": 0, "on": 1, "all": 2}
+
+
+def set_slab_split(mode):
+    """Slab split of the lane refine's longest cone walks for later calls:
+    "auto" (from d = 7 and 2^18 points), "off", "on" or "all" (as many cells
+    as the item array has room for; for tests)."""
+    _check(lib().skycell_set_slab_split(SLAB_SPLIT_MODES[mode]))
 
 
 CELL_PRUNE_FORMS = {"prefix_or": 0, "tree": 1}

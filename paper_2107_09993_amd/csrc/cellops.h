@@ -145,16 +145,83 @@ __device__ __forceinline__ void scatter_point(const T *__restrict__ pts, uint32_
     sidx[pos] = (int32_t)i;
 }
 
+// ---- slabs of long cone walks (walk-record lane form)
+// The cost of a lane-form work item is the length of its cell's cone walk,
+// which is heavy-tailed (on the anti-correlated headline data the median walk
+// is 54 visits, the 99th percentile 1,139, and the longest 1% of items make
+// 12% of the visits).  A long walk handed out late holds its wave, and the
+// launch, after the other waves are done.  The odometer walk lowers dimension
+// d-1 last, so the cone of cell x is the union of its slabs s = 0..c[d-1]:
+// the cells whose column d-1 is c[d-1] - s, walked from the corner
+// x - s e_{d-1} in dimensions 0..d-2 only.  The slabs are independent walks
+// over the same candidates, so a query point is dominated iff some slab finds
+// a dominator.  The cells whose cone-size estimate sum_k log2(c_k + 1) (a
+// correlation of 0.70 with the log of the walk length on the headline data)
+// is in the top bins (k_split_pick) get one work item per (query group, slab),
+// next to each other in Morton order, so the slabs run on neighbouring lanes
+// at the same time and keep the locality of the cone walks.
+constexpr int kSplitBins = 256;
+
+// Column of cell x in the dimension whose index bits are m.
+__device__ __forceinline__ uint32_t cell_column(uint32_t x, uint32_t m)
+{
+    uint32_t c = 0u, bit = 1u;
+    while (m != 0u) {
+        const uint32_t low = m & (0u - m);
+        if (x & low) c |= bit;
+        bit <<= 1;
+        m ^= low;
+    }
+    return c;
+}
+
+// Cone-size estimate of cell x: prod_k (c_k + 1), the number of cells <= x,
+// from the r bit planes of its Morton index.
+__device__ __forceinline__ float cone_cells(const GridDesc &gd, uint32_t x)
+{
+    float p = 1.0f;
+    for (int k = 0; k < gd.d; ++k) {
+        uint32_t c = 0u;
+        for (int b = 0; b < gd.r; ++b) c |= ((x >> (b * gd.d + k)) & 1u) << b;
+        p *= (float)(c + 1u);
+    }
+    return p;
+}
+
+// Histogram bin of a cone-size estimate: 4 log2, rounded, below kSplitBins.
+__device__ __forceinline__ uint32_t cone_bin(float cells)
+{
+    const uint32_t b = (uint32_t)(4.0f * __log2f(cells) + 0.5f);
+    return b < (uint32_t)kSplitBins ? b : (uint32_t)kSplitBins - 1u;
+}
+
+// Slabs of a cell's items from its record (rec_slabs: c[d-1] + 1 for a split
+// cell, else 0), or 1 for every cell if the split's added items do not fit in
+// the n slots of the item array (the record pass counts both exactly).
+__device__ __forceinline__ uint32_t cell_slabs(uint64_t r, const uint32_t *__restrict__ ctr, uint32_t n)
+{
+    const uint32_t s = rec_slabs(r);
+    if (s == 0u) return 1u;
+    const uint64_t need = (uint64_t)ctr[kCtrSplitItems] + ctr[kCtrSplitExtra];
+    return (ctr[kCtrSplitFail] == 0u && need <= n) ? s : 1u;
+}
+
 // Scan value per cell: surviving points (low 32 bits) and refine work items
-// (high 32 bits); a cell with m surviving points gives ceil(m / M) items.
+// (high 32 bits); a cell with m surviving points gives ceil(m / M) items, times
+// its slabs when long walks are split (slabs: the per-cell slab bytes, or
+// null).
 struct CellLoader {
     const uint64_t *rec;
     const uint32_t *cnt;
     uint32_t per_item;
+    const uint32_t *ctr;  // with split slabs (else null): the split counters
+    uint32_t n;
     __device__ uint64_t operator()(uint64_t x) const
     {
-        const uint32_t m = rec_surv(rec[x]) ? cnt[x] : 0u;
-        const uint32_t it = (m + per_item - 1u) / per_item;
+        const uint64_t r = rec[x];
+        const uint32_t m = rec_surv(r) ? cnt[x] : 0u;
+        uint32_t it = (m + per_item - 1u) / per_item;
+        if (ctr != nullptr && m != 0u) it *= cell_slabs(r, ctr, n);
         return (uint64_t)m | ((uint64_t)it << 32);
     }
 };
@@ -162,11 +229,17 @@ struct CellLoader {
 // Writes the first sorted position into the low half of the cell record and
 // the cell's work items: (first sorted position, (point count << 26) | cell).
 // With `recount`, the record's count field is rewritten from the scanned count.
+// With slabs, the items of a split cell are its query groups times its
+// slabs, slab-minor: item t is group t / S, slab t % S, rooted at the slab's
+// corner and flagged kItemSlab.
 struct CellEmitter {
     uint32_t *rec_words;
     uint2 *items;
     uint32_t per_item;
     bool recount;
+    bool split;           // the loader may have split cells into slabs
+    uint32_t top_mask;    // index bits of dimension d-1
+    uint32_t cap;  // slots of the item array (n); never written past
     __device__ void operator()(uint64_t x, uint64_t prefix, uint64_t v) const
     {
         const uint32_t start = (uint32_t)prefix;
@@ -178,8 +251,11 @@ struct CellEmitter {
         }
         const uint32_t it = (uint32_t)(v >> 32);
         const uint32_t ibase = (uint32_t)(prefix >> 32);
+        // the loader multiplied the cell's query groups by its slabs
+        const uint32_t groups = (m + per_item - 1u) / per_item;
+        const uint32_t ns = (split && groups != 0u) ? it / groups : 1u;
         const uint32_t own = it < kLaneItems ? it : kLaneItems;
-        for (uint32_t t = 0; t < own; ++t) put(ibase, start, m, (uint32_t)x, t);
+        for (uint32_t t = 0; t < own; ++t) put(ibase, start, m, (uint32_t)x, t, ns);
         // A cell with more items than one lane writes alone (on correlated data
         // a few cells can hold most of the points, thousands of items each) is
         // finished by every active lane of the wave together, consecutive lanes
@@ -198,15 +274,23 @@ struct CellEmitter {
             const uint32_t bm = __builtin_amdgcn_readlane(m, l);
             const uint32_t bx = __builtin_amdgcn_readlane((uint32_t)x, l);
             const uint32_t bi = __builtin_amdgcn_readlane(it, l);
-            for (uint32_t t = kLaneItems + pos; t < bi; t += nact) put(bb, bs, bm, bx, t);
+            const uint32_t bsl = __builtin_amdgcn_readlane(ns, l);
+            for (uint32_t t = kLaneItems + pos; t < bi; t += nact) put(bb, bs, bm, bx, t, bsl);
         }
     }
     static constexpr uint32_t kLaneItems = 8;
-    __device__ void put(uint32_t ibase, uint32_t start, uint32_t m, uint32_t x, uint32_t t) const
+    __device__ void put(uint32_t ibase, uint32_t start, uint32_t m, uint32_t x, uint32_t t, uint32_t ns) const
     {
-        const uint32_t first = t * per_item;
+        const uint32_t grp = t / ns, slab = t - grp * ns;
+        const uint32_t first = grp * per_item;
         const uint32_t c = (m - first) < per_item ? (m - first) : per_item;
-        items[ibase + t] = make_uint2(start + first, (c << 26) | x);
+        uint32_t root = x, flag = 0u;
+        if (ns > 1u) {
+            // x - slab * e_{d-1}: a masked subtraction in dimension d-1's bits
+            root = (((x & top_mask) - deposit_bits(slab, top_mask)) & top_mask) | (x & ~top_mask);
+            flag = kItemSlab;
+        }
+        if (ibase + t < cap) items[ibase + t] = make_uint2(start + first, (c << 26) | root | flag);
     }
 };
 

@@ -18,7 +18,8 @@ constexpr int kWave = 64;
 //                end is the next record's start)
 //   bits 47..62  lower-neighbour mask: bit k set iff the cell one column lower
 //                in dimension k exists and some non-empty cell lies in its
-//                lower cone
+//                lower cone; for d <= 8 bits 55..62 hold the cell's slab count
+//                when the lane form splits its items (cellops.h), else 0
 //   bit  63      surviving non-empty cell: it holds points and no non-empty
 //                cell has a smaller column in every dimension (Definition 3)
 constexpr uint32_t kRecCountSat = 0x7FFFu;
@@ -26,6 +27,7 @@ __host__ __device__ __forceinline__ uint32_t rec_start(uint64_t r) { return (uin
 __host__ __device__ __forceinline__ uint32_t rec_count(uint64_t r) { return (uint32_t)(r >> 32) & kRecCountSat; }
 __host__ __device__ __forceinline__ uint32_t rec_nbr(uint64_t r) { return (uint32_t)(r >> 47) & 0xFFFFu; }
 __host__ __device__ __forceinline__ bool rec_surv(uint64_t r) { return (r >> 63) != 0u; }
+__host__ __device__ __forceinline__ uint32_t rec_slabs(uint64_t r) { return (uint32_t)(r >> 55) & 0xFFu; }
 
 // Coarse screening keys: every coordinate also gets a 7-bit column on a
 // 128-column grid (same non-decreasing map as the cell columns), packed one
@@ -64,6 +66,8 @@ struct GridDesc {
     int32_t parts;             // wave form: waves that share one item's cone (>= 1)
     int32_t tile;              // 1: tile form of the refine (refine_tile.hip)
     int32_t plain;             // 1: lane form without the walk records' minimum corners
+    int32_t split;             // 1: the longest cone walks of the lane form are split into slabs (cellops.h),
+                               // 2: as many as the item array has room for
 };
 
 // Index of the cell one column lower / higher in the dimension whose bits are
@@ -171,8 +175,12 @@ enum CtrIndex {
     kCtrSurvPts = 2,   // number of surviving points
     kCtrPivSampled = 3,  // pivot pre-filter: sampled points of surviving cells
     kCtrPivHit = 4,      // ... of which a pivot dominates
+    kCtrSplitThr = 5,    // float bits: cells whose cone-size product reaches it are split into slabs
+    kCtrSplitItems = 6,  // work items of the surviving cells before the split
+    kCtrSplitExtra = 7,  // items the split adds (no cell is split if they do not fit in n)
     kCtrHead = 8,      // kNumXcd refine work-queue heads, one per XCD share
-    kCtrCount = 16     // number of 32-bit counters reserved
+    kCtrSplitFail = 16,  // nonzero: the split's added items passed the room (or wrapped)
+    kCtrCount = 17     // number of 32-bit counters reserved
 };
 
 size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *base);
@@ -181,10 +189,13 @@ size_t workspace_layout(int64_t n, int d, uint32_t cells, Workspace *ws, char *b
 hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats, hipStream_t st);
 hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                                 int value_bits, const Workspace &ws, hipStream_t st);
-hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st);
+// With gd.split, also picks the cells whose items are split into slabs
+// (cellops.h); only for callers whose cell records stay as this pass writes
+// them, since the split keeps the items within the n slots of the item array.
+hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, int64_t n, uint64_t *stats, hipStream_t st);
 // recount: the cell counts were taken again after the pivot pre-filter; the
 // count field of every record is rewritten from them.
-hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st,
+hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, int64_t n, uint64_t *stats, hipStream_t st,
                             bool recount = false);
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                           const Workspace &ws, int value_bits, int num_cus, hipStream_t st);
@@ -196,9 +207,20 @@ hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc 
 constexpr int64_t kWrecMaxPoints = (int64_t)1 << 28;
 static_assert((kMaxD & (kMaxD - 1)) == 0, "the walk's shared tables are indexed modulo kMaxD");
 inline bool lane_mc(const GridDesc &gd) { return gd.d <= kWrecMaxD && gd.plain == 0; }
+// Work items of the walk-record lane form whose cone walks are expected to be
+// the longest are split into one item per slab of the cone (cellops.h); the
+// item flag of such a slab item:
+constexpr uint32_t kItemSlab = 1u << 31;
+inline bool lane_split(const GridDesc &gd)
+{
+    return lane_mc(gd) && gd.tile == 0 && gd.m != kWaveItemPoints && gd.d >= 2;
+}
+// Work items per split item (SKYCELL_SPLIT_SHARE overrides it for tuning
+// sweeps; 0 splits nothing).
+uint32_t split_share();
 // Walk records of the lane form (walk_records.hip), built from the sorted
 // points; launch_scatter ends with it.
-hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, hipStream_t st);
+hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, int64_t n, hipStream_t st);
 hipError_t launch_refine(int64_t n, const GridDesc &gd, const Workspace &ws, uint64_t *stats,
                          int num_cus, hipStream_t st);
 hipError_t refine_prepare(const GridDesc &gd);

@@ -278,7 +278,7 @@ int skycell_compute_layered(const void *points, int32_t dtype, int64_t n, int32_
                            (uint32_t)n, d, (uint32_t)(1u << rho), value_bits, (const uint32_t *)ws.cell_of, ws.rank,
                            occ);
     SKYCELL_HIP_CHECK(hipGetLastError());
-    SKYCELL_HIP_CHECK(launch_cell_prune(gd, ws, nullptr, st));
+    SKYCELL_HIP_CHECK(launch_cell_prune(gd, ws, n, nullptr, st));
     switch (d) {
 #define SKYCELL_FINE_CASE(DD)                                                                                    \
     case DD:                                                                                                     \
@@ -302,7 +302,7 @@ int skycell_compute_layered(const void *points, int32_t dtype, int64_t n, int32_
     hipLaunchKernelGGL(k_fine_prune, fine_grid(n), dim3(kFineThreads), 0, st, (uint32_t)n, d,
                        (const uint32_t *)ws.cell_of, (const uint64_t *)ws.rec, (const uint32_t *)dom, ws.rank, ws.cnt);
     SKYCELL_HIP_CHECK(hipGetLastError());
-    SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st, true));
+    SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, n, stats, st, true));
     SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, value_bits, cus, st));
     SKYCELL_HIP_CHECK(launch_refine(n, gd, ws, stats, cus, st));
     SKYCELL_HIP_CHECK(launch_output(n, ws, out_idx, out_count, stats, st));

@@ -55,14 +55,21 @@ static inline dim3 grid_for(uint64_t count, int per_block = kThreads)
 
 // ------------------------------------------------------------------ init
 __global__ __launch_bounds__(kThreads) void k_init(uint32_t *cnt, uint32_t cells, uint32_t *ctr,
-                                                   uint64_t *stats, int32_t g)
+                                                   uint64_t *stats, int32_t g, uint32_t *split_hist)
 {
     const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t stride = gridDim.x * kThreads;
     for (uint32_t i = gid; i < cells; i += stride) cnt[i] = 0u;
-    if (gid < kCtrCount) ctr[gid] = 0u;
+    if (split_hist != nullptr)
+        for (uint32_t i = gid; i <= (uint32_t)kSplitBins; i += stride) split_hist[i] = 0u;
+    if (gid < kCtrCount) ctr[gid] = gid == kCtrSplitThr ? 0x7F800000u : 0u;  // threshold +inf: no cell split
     if (stats != nullptr && gid < SKYCELL_NUM_STATS)
         stats[gid] = gid == SKYCELL_STAT_GRID_RES ? (uint64_t)g : 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_words(uint32_t *__restrict__ p, uint32_t count)
+{
+    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < count; t += gridDim.x * kThreads) p[t] = 0u;
 }
 
 hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats, hipStream_t st)
@@ -70,7 +77,8 @@ hipError_t launch_init(const Workspace &ws, const GridDesc &gd, uint64_t *stats,
     uint32_t blocks = (gd.cells + kThreads * 8 - 1) / (kThreads * 8);
     if (blocks < 1) blocks = 1;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kThreads), 0, st, ws.cnt, gd.cells, ws.ctr, stats, gd.g);
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kThreads), 0, st, ws.cnt, gd.cells, ws.ctr, stats, gd.g,
+                       gd.split ? ws.bcur : nullptr);
     return hipGetLastError();
 }
 
@@ -236,24 +244,72 @@ __global__ __launch_bounds__(kThreads) void k_lc_step(uint64_t *__restrict__ lcb
 // in the low half (first sorted position).  Grid-stride over the cells, so that
 // with statistics on, each workgroup adds its totals with one atomic per
 // counter at the end (one atomic per wave on the same two words serialised).
+// With `split` (lane form with split slabs): the slab count of every
+// surviving cell whose cone-size estimate reaches the picked threshold goes
+// into its record (rec_slabs), and the exact work items before the split and
+// the items it adds are counted (cell_slabs checks that they fit in n).
 constexpr uint32_t kCellRecBlocks = 2048;
 
 __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32_t *__restrict__ cnt,
                                                        const uint64_t *__restrict__ lc,
                                                        uint64_t *__restrict__ rec,
                                                        uint64_t *__restrict__ survbits,
-                                                       uint64_t *__restrict__ stats)
+                                                       uint64_t *__restrict__ stats,
+                                                       uint32_t *__restrict__ split, uint32_t per_item)
 {
+    float thr = __builtin_inff();
+    if (split != nullptr) thr = __uint_as_float(split[kCtrSplitThr]);
+    const uint32_t top = gd.mask[gd.d - 1];
     uint32_t nocc = 0u, nsurv = 0u;  // wave-uniform running totals
+    uint64_t items_all = 0ull, extra = 0ull;  // per lane
     for (uint32_t base = blockIdx.x * kThreads; base < gd.cells; base += gridDim.x * kThreads) {
         const uint32_t x = base + threadIdx.x;
         bool occ = false, surv = false;
-        if (x < gd.cells) rec[x] = cell_record(gd, cnt, lc, x, occ, surv);
+        uint64_t r = 0ull;
+        if (x < gd.cells) r = cell_record(gd, cnt, lc, x, occ, surv);
+        if (split != nullptr && surv) {
+            const uint32_t items = (cnt[x] + per_item - 1u) / per_item;
+            items_all += items;
+            const uint32_t c = cell_column(x, top);
+            if (c >= 1u && cone_cells(gd, x) >= thr) {
+                r |= (uint64_t)(c + 1u) << 55;
+                extra += (uint64_t)items * c;
+            }
+        }
+        if (x < gd.cells) rec[x] = r;
         // one bitmap word per wave: the wave's 64 cells start at a multiple of 64
         const uint64_t bs = __ballot(surv);
         if (__lane_id() == 0 && x < gd.cells) survbits[x >> 6] = bs;
         nocc += (uint32_t)__popcll(__ballot(occ));
         nsurv += (uint32_t)__popcll(bs);
+    }
+    if (split != nullptr) {
+        __shared__ uint64_t s_part[2][kThreads / kWave];
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            items_all += __shfl_xor(items_all, off);
+            extra += __shfl_xor(extra, off);
+        }
+        if (__lane_id() == 0) {
+            s_part[0][threadIdx.x / kWave] = items_all;
+            s_part[1][threadIdx.x / kWave] = extra;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t ti = 0ull, te = 0ull;
+            for (int w = 0; w < kThreads / kWave; ++w) {
+                ti += s_part[0][w];
+                te += s_part[1][w];
+            }
+            // both totals are below n < 2^31 when the split fits; a sum that
+            // passes 2^31 marks it as not fitting, for good
+            if (ti != 0ull) atomicAdd(&split[kCtrSplitItems], (uint32_t)ti);
+            if (te >= (1ull << 31)) {
+                atomicOr(&split[kCtrSplitFail], 1u);
+            } else if (te != 0ull) {
+                const uint32_t old = atomicAdd(&split[kCtrSplitExtra], (uint32_t)te);
+                if ((uint64_t)old + te >= (1ull << 31)) atomicOr(&split[kCtrSplitFail], 1u);
+            }
+        }
     }
     if (stats != nullptr) {
         __shared__ uint32_t s_occ[kThreads / kWave], s_surv[kThreads / kWave];
@@ -274,7 +330,71 @@ __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32
     }
 }
 
-hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st)
+uint32_t split_share()
+{
+    static int share = -1;
+    if (share < 0) {
+        const char *v = getenv("SKYCELL_SPLIT_SHARE");
+        share = v ? atoi(v) : 512;
+        if (share < 0) share = 512;
+    }
+    return (uint32_t)share;
+}
+
+// The split's threshold from a sample of the occupied cells: runs of 256
+// consecutive cells, one run in `stride` (kSplitSample on grids of more than
+// 2^20 cells, else every run).  hist[b] takes the work items (per_item points
+// each) of the sampled cells with more than one slab whose cone-size bin is b,
+// hist[kSplitBins] those of every sampled cell.
+constexpr uint32_t kSplitSample = 16;
+
+__global__ __launch_bounds__(kThreads) void k_split_hist(GridDesc gd, const uint32_t *__restrict__ cnt,
+                                                         uint32_t per_item, uint32_t stride,
+                                                         uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_hist[kSplitBins + 1];
+    for (int b = threadIdx.x; b <= kSplitBins; b += kThreads) s_hist[b] = 0u;
+    __syncthreads();
+    const uint32_t top = gd.mask[gd.d - 1];
+    const uint32_t runs = (gd.cells + kThreads - 1u) / kThreads;
+    for (uint32_t run = blockIdx.x * stride; run < runs; run += gridDim.x * stride) {
+        const uint32_t x = run * kThreads + threadIdx.x;
+        const uint32_t m = x < gd.cells ? cnt[x] : 0u;
+        if (m != 0u) {
+            const uint32_t items = (m + per_item - 1u) / per_item;
+            atomicAdd(&s_hist[kSplitBins], items);
+            if (cell_column(x, top) >= 1u) atomicAdd(&s_hist[cone_bin(cone_cells(gd, x))], items);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b <= kSplitBins; b += kThreads)
+        if (s_hist[b] != 0u) atomicAdd(&hist[b], s_hist[b]);
+}
+
+// One thread: the lowest bin B whose sampled items and above are at most
+// 1 / share of all items (share 0: as many as the item array's estimated room
+// takes), and never more than that room over g - 1 (a split cell's items
+// become at most g times as many); the threshold is the smallest cone-size
+// estimate of bin B (cells at or above it are split, cellops.h).
+__global__ void k_split_pick(const uint32_t *__restrict__ hist, uint32_t share, uint32_t n, uint32_t g,
+                             uint32_t stride, uint32_t *__restrict__ ctr)
+{
+    const uint64_t total = (uint64_t)hist[kSplitBins] * stride;
+    const uint64_t room = total < n ? ((uint64_t)n - total) / (g > 1u ? g - 1u : 1u) : 0ull;
+    uint64_t target = share != 0u ? total / share : room;
+    if (target > room) target = room;
+    target /= stride;  // in sampled items
+    uint64_t acc = 0ull;
+    uint32_t b = (uint32_t)kSplitBins;
+    while (b > 1u && acc + hist[b - 1u] <= target) {  // bin 0: cone of one cell
+        acc += hist[b - 1u];
+        --b;
+    }
+    const float thr = b >= (uint32_t)kSplitBins ? __builtin_inff() : exp2f(((float)b - 0.5f) * 0.25f);
+    ctr[kCtrSplitThr] = __float_as_uint(thr);
+}
+
+hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, int64_t n, uint64_t *stats, hipStream_t st)
 {
     hipLaunchKernelGGL(k_lc_init, grid_for(gd.cells), dim3(kThreads), 0, st, ws.cnt, ws.lc, gd.cells);
     if (gd.g > 1) {
@@ -292,8 +412,20 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, uint64_t *
     }
     dim3 rgrid = grid_for(gd.cells);
     if (rgrid.x > kCellRecBlocks) rgrid.x = kCellRecBlocks;
+    const bool split = gd.split != 0;
+    if (split) {
+        const uint32_t runs = (gd.cells + kThreads - 1u) / kThreads;
+        const uint32_t stride = gd.cells > (1u << 20) ? kSplitSample : 1u;
+        uint32_t hb = (runs + stride - 1u) / stride;
+        if (hb > 512u) hb = 512u;
+        hipLaunchKernelGGL(k_split_hist, dim3(hb), dim3(kThreads), 0, st, gd, (const uint32_t *)ws.cnt,
+                           (uint32_t)gd.m, stride, ws.bcur);
+        // gd.split 2: as many cells as the item array has room for (tests)
+        hipLaunchKernelGGL(k_split_pick, dim3(1), dim3(1), 0, st, (const uint32_t *)ws.bcur,
+                           gd.split == 2 ? 0u : split_share(), (uint32_t)n, (uint32_t)gd.g, stride, ws.ctr);
+    }
     hipLaunchKernelGGL(k_cell_rec, rgrid, dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
-                       ws.rec, ws.survbits, stats);
+                       ws.rec, ws.survbits, stats, split ? ws.ctr : nullptr, (uint32_t)gd.m);
     return hipGetLastError();
 }
 
@@ -311,12 +443,13 @@ __global__ void k_cell_scan_total(const uint64_t *block_sums, uint32_t nb, uint3
     }
 }
 
-hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, uint64_t *stats, hipStream_t st,
+hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, int64_t n, uint64_t *stats, hipStream_t st,
                             bool recount)
 {
     const uint32_t m = (uint32_t)gd.m;
-    CellLoader ld{ws.rec, ws.cnt, m};
-    CellEmitter em{(uint32_t *)ws.rec, ws.items, m, recount};
+    const uint32_t *split = gd.split ? ws.ctr : nullptr;
+    CellLoader ld{ws.rec, ws.cnt, m, split, (uint32_t)n};
+    CellEmitter em{(uint32_t *)ws.rec, ws.items, m, recount, split != nullptr, gd.mask[gd.d - 1], (uint32_t)n};
     hipError_t e = enqueue_scan<uint64_t>(ld, em, gd.cells, ws.block_sums, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cell_scan_total, dim3(1), dim3(1), 0, st, (const uint64_t *)ws.block_sums,
@@ -558,11 +691,6 @@ static uint32_t scatter_buckets_for(int64_t n, uint32_t cells)
     return nb < cells ? nb : cells;
 }
 
-__global__ __launch_bounds__(kThreads) void k_zero_words(uint32_t *__restrict__ p, uint32_t count)
-{
-    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < count; t += gridDim.x * kThreads) p[t] = 0u;
-}
-
 template <typename T>
 static hipError_t launch_scatter_two_pass(const T *pts, int64_t n, const GridDesc &gd, const Workspace &ws,
                                           int value_bits, int num_cus, hipStream_t st)
@@ -623,7 +751,7 @@ hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc 
 {
     const hipError_t e = launch_scatter_points(pts, dtype, n, gd, ws, value_bits, num_cus, st);
     if (e != hipSuccess) return e;
-    return launch_walk_records(gd, ws, st);
+    return launch_walk_records(gd, ws, n, st);
 }
 
 // ------------------------------------------------------------------ scan partials

@@ -167,6 +167,7 @@ static int items_per_lane(int d)
 // tuning table's form for this (d, n, dtype) and grid, else the wave form when
 // the grid is very coarse (at least 32 points per cell of the index space on
 // average), where cells hold enough points to keep a wave busy.
+static std::atomic<int> g_split_override{-1};  // slab split: -1 auto, 0 off, 1 on, 2 all that fit
 static std::atomic<int> g_form_override{-2};  // -2 unread, -1 none, 0 lane, 1 wave, 2 tile, 3 plain lane
 
 // The form the table (or the rule) gives, without the override.
@@ -428,7 +429,21 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
                  int32_t value_bits, int32_t *out_idx, int32_t *out_count, void *workspace,
                  uint64_t *stats, hipStream_t st, const PivotArgs *piv, const TreeScratch *tree, int cls)
 {
-    const GridDesc gd = pipeline_desc(n, d, g, dtype, cls);
+    GridDesc gd = pipeline_desc(n, d, g, dtype, cls);
+    // Slab split of the longest cone walks (cellops.h): measured on one MI355X,
+    // anti-correlated n = 10^7, d = 8: 8.31 -> 8.16 ms per call; n = 10^6,
+    // d = 8: -10%; but d = 6 (n = 10^7, uint16) +2% and n = 10^4 +4% (two more
+    // launches), so it runs from d = 7 and 2^18 points.  The paper's tree prune
+    // rewrites the cell records after the prefix-OR pass, so the split (sized
+    // by that pass) stays off with it.
+    const int split_mode = g_split_override.load();
+    const bool split_auto = d >= 7 && n >= ((int64_t)1 << 18);
+    if (tree == nullptr && lane_split(gd)) {
+        if (split_mode == 2)
+            gd.split = 2;
+        else if (split_share() > 0u && (split_mode == 1 || (split_mode == -1 && split_auto)))
+            gd.split = 1;
+    }
     Workspace ws;
     workspace_layout(n, d, gd.cells, &ws, (char *)workspace);
     int dev = 0;
@@ -438,7 +453,7 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
     SKYCELL_HIP_CHECK(launch_init(ws, gd, stats, st));
     SKYCELL_HIP_CHECK(launch_quantize_hist(points, dtype, n, gd, value_bits, ws, st));
     SKYCELL_PROF(1);
-    SKYCELL_HIP_CHECK(launch_cell_prune(gd, ws, stats, st));
+    SKYCELL_HIP_CHECK(launch_cell_prune(gd, ws, n, stats, st));
     if (tree != nullptr) {
         const int rho = gd.r;
         SKYCELL_HIP_CHECK(run_shrink_tree(ws.cnt, d, rho, *tree, nullptr, nullptr, st));
@@ -452,7 +467,7 @@ int run_pipeline(const void *points, int32_t dtype, int64_t n, int32_t d, int g,
                                              g_pivot_gate.load() != 0, st));
     }
     SKYCELL_PROF(2);
-    SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, stats, st, pivots));
+    SKYCELL_HIP_CHECK(launch_cell_scan(gd, ws, n, stats, st, pivots));
     SKYCELL_PROF(3);
     SKYCELL_HIP_CHECK(launch_scatter(points, dtype, n, gd, ws, value_bits, cus, st));
     SKYCELL_PROF(4);
@@ -650,6 +665,13 @@ int skycell_set_refine_form(int32_t form)
 {
     if (form < -1 || form > 3) return fail(SKYCELL_E_INVAL, "form = %d is not -1, 0, 1, 2 or 3", form);
     g_form_override.store(form);
+    return ok();
+}
+
+int skycell_set_slab_split(int32_t mode)
+{
+    if (mode < -1 || mode > 2) return fail(SKYCELL_E_INVAL, "mode = %d is not -1, 0, 1 or 2", mode);
+    g_split_override.store(mode);
     return ok();
 }
 

@@ -82,6 +82,7 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
         q6[t] = kGuard;
     }
     uint32_t alive = 0u, qstart = 0u, qcnt = 0u;
+    bool slab = false;  // the item walks one slab of its cell's cone (cellops.h)
     uint32_t root = 0u, x = 0u, diag = 0u;
     bool walking = false;
     uint32_t cur = 0u, end = 0u, pcur = 0u, pend = 0u;
@@ -159,7 +160,8 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
 
         // ---- item setup
         if (st == 1) {
-            qcnt = it.y >> 26;
+            qcnt = (it.y >> 26) & 31u;
+            slab = (it.y & kItemSlab) != 0u;
             qstart = it.x;
             root = it.y & ((1u << 26) - 1u);
             st = 2;
@@ -176,7 +178,7 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
             }
             alive = (1u << qcnt) - 1u;
             x = root;
-            diag = rec_nbr(r0) & kAll;
+            diag = rec_nbr(r0) & (slab ? kAll >> 1 : kAll);  // a slab stays in dimensions 0..D-2
             walking = true;
             cur = rec_start(r0);
             uint32_t c = rec_count(r0);
@@ -293,15 +295,15 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
         }
 
         // ---- item end
-        if (active) {
-            if (alive == 0u) {
-                st = 0;
-            } else if (!walking && !rqv && cur >= end && pcur >= pend && exmask == 0u) {
+        // (a whole-cone item sets the flags of its surviving query points; a
+        // slab item, whose points start flagged, clears those it found dominated)
+        if (active && (alive == 0u || (!walking && !rqv && cur >= end && pcur >= pend && exmask == 0u))) {
 #pragma unroll
-                for (int t = 0; t < M; ++t)
-                    if (alive & (1u << t)) v.flag[v.sidx[qstart + t]] = 1;
-                st = 0;
+            for (int t = 0; t < M; ++t) {
+                const bool live = (alive >> t) & 1u;
+                if ((uint32_t)t < qcnt && live != slab) v.flag[v.sidx[qstart + t]] = live ? 1 : 0;
             }
+            st = 0;
         }
     }
 }

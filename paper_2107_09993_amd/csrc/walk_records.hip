@@ -47,10 +47,16 @@ __device__ __forceinline__ uint64_t fields_min(uint64_t a, uint64_t b)
     return (a & sel) | (b & ~sel);
 }
 
+// With slabs (lane form with split cones, cellops.h), the output flags of the
+// points of every split cell are set: its slab items clear the flags of the
+// points they find dominated.
 template <int D>
 __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restrict__ rec,
                                                          const uint64_t *__restrict__ fkeys,
-                                                         uint64_t *__restrict__ wrec, int r, int pdims, int tb)
+                                                         uint64_t *__restrict__ wrec, int r, int pdims, int tb,
+                                                         const uint32_t *__restrict__ ctr_split, uint32_t n,
+                                                         const int32_t *__restrict__ sidx,
+                                                         uint8_t *__restrict__ flag)
 {
     constexpr uint32_t kAll = (1u << D) - 1u;
     constexpr uint64_t kNone = 0x7F7F7F7F7F7F7F7Full;
@@ -109,6 +115,13 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
                 if (c[q] == kRecCountSat) c[q] = rec_start(rec[xi[q] + 1]) - s[q];
             }
         }
+        bool split[kWrecBatch];
+#pragma unroll
+        for (int q = 0; q < kWrecBatch; ++q) {
+            split[q] = ctr_split != nullptr && c[q] != 0u && cell_slabs(rr[q], ctr_split, n) > 1u;
+            if (split[q] && c[q] <= kWrecLanePoints)
+                for (uint32_t i = 0; i < c[q]; ++i) flag[sidx[s[q] + i]] = 1;
+        }
         uint64_t mn[kWrecBatch];
 #pragma unroll
         for (int q = 0; q < kWrecBatch; ++q) {
@@ -127,8 +140,12 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
                 big &= big - 1ull;
                 const uint32_t bs = __builtin_amdgcn_readlane(s[q], l);
                 const uint32_t bc = __builtin_amdgcn_readlane(c[q], l);
+                const bool bsplit = __builtin_amdgcn_readlane(split[q] ? 1u : 0u, l) != 0u;
                 uint64_t part = kNone;
-                for (uint32_t i = __lane_id(); i < bc; i += kWave) part = bytes_min(part, fkeys[bs + i]);
+                for (uint32_t i = __lane_id(); i < bc; i += kWave) {
+                    part = bytes_min(part, fkeys[bs + i]);
+                    if (bsplit) flag[sidx[bs + i]] = 1;
+                }
                 for (int off = kWave / 2; off > 0; off >>= 1) part = bytes_min(part, __shfl_xor(part, off));
                 if (__lane_id() == (unsigned)l) mn[q] = part;
             }
@@ -172,7 +189,7 @@ __global__ __launch_bounds__(kWrecThreads) void k_wrec(const uint64_t *__restric
 
 // Walk records for the lane form's minimum-corner screen (after the scatter;
 // nothing to do for the other forms).
-hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, hipStream_t st)
+hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, int64_t n, hipStream_t st)
 {
     if (gd.tile || gd.m == kWaveItemPoints || !lane_mc(gd)) return hipSuccess;
     const int pdims = wrec_prefix_dims(gd.d, gd.r);
@@ -183,7 +200,9 @@ hipError_t launch_walk_records(const GridDesc &gd, const Workspace &ws, hipStrea
 #define SKYCELL_WREC_CASE(DD)                                                                            \
     case DD:                                                                                             \
         hipLaunchKernelGGL((k_wrec<DD>), dim3(tiles), dim3(kWrecThreads), 0, st, (const uint64_t *)ws.rec, \
-                           (const uint64_t *)ws.fkeys, ws.wrec, gd.r, pdims, tb);                        \
+                           (const uint64_t *)ws.fkeys, ws.wrec, gd.r, pdims, tb,                         \
+                           gd.split ? (const uint32_t *)ws.ctr : nullptr, (uint32_t)n,                             \
+                           (const int32_t *)ws.sidx, ws.flag);                                           \
         return hipGetLastError();
         SKYCELL_WREC_CASE(1)
         SKYCELL_WREC_CASE(2)

@@ -181,6 +181,15 @@ def test_refine_form_argument_errors():
     sky.set_refine_form("auto")
 
 
+def test_slab_split_argument_errors():
+    lib = sky.lib()
+    for bad in (-2, 3):
+        assert lib.skycell_set_slab_split(bad) == sky.E_INVAL
+    for mode in sky.SLAB_SPLIT_MODES:
+        sky.set_slab_split(mode)
+    sky.set_slab_split("auto")
+
+
 def test_batched_plan_argument_errors():
     import numpy as np
     lib = sky.lib()
