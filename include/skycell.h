@@ -277,7 +277,7 @@ int skycell_set_cell_prune(int32_t form);
 /*
  * Slab split of the lane refine for all later calls in the process (d <= 8,
  * lane form with minimum corners): the cells with the largest cone-size
- * estimate prod_k (c_k + 1), about 1/512 of the work items, get one work item
+ * estimate prod_k (c_k + 1), about 1/256 of the work items, get one work item
  * per slab of their lower cone (the cells with one column of dimension d-1,
  * walked in dimensions 0..d-2), so that the longest cone walks run in
  * parallel on neighbouring lanes instead of holding one lane, and the launch,

@@ -160,7 +160,7 @@ __device__ __forceinline__ void scatter_point(const T *__restrict__ pts, uint32_
 // is in the top bins (k_split_pick) get one work item per (query group, slab),
 // next to each other in Morton order, so the slabs run on neighbouring lanes
 // at the same time and keep the locality of the cone walks.
-constexpr int kSplitBins = 256;
+constexpr int kSplitBins = 512;
 
 // Column of cell x in the dimension whose index bits are m.
 __device__ __forceinline__ uint32_t cell_column(uint32_t x, uint32_t m)
@@ -188,10 +188,10 @@ __device__ __forceinline__ float cone_cells(const GridDesc &gd, uint32_t x)
     return p;
 }
 
-// Histogram bin of a cone-size estimate: 4 log2, rounded, below kSplitBins.
+// Histogram bin of a cone-size estimate: 8 log2, rounded, below kSplitBins.
 __device__ __forceinline__ uint32_t cone_bin(float cells)
 {
-    const uint32_t b = (uint32_t)(4.0f * __log2f(cells) + 0.5f);
+    const uint32_t b = (uint32_t)(8.0f * __log2f(cells) + 0.5f);
     return b < (uint32_t)kSplitBins ? b : (uint32_t)kSplitBins - 1u;
 }
 

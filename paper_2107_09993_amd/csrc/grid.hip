@@ -335,18 +335,21 @@ uint32_t split_share()
     static int share = -1;
     if (share < 0) {
         const char *v = getenv("SKYCELL_SPLIT_SHARE");
-        share = v ? atoi(v) : 512;
-        if (share < 0) share = 512;
+        share = v ? atoi(v) : 256;
+        if (share < 0) share = 256;
     }
     return (uint32_t)share;
 }
 
 // The split's threshold from a sample of the occupied cells: runs of 256
 // consecutive cells, one run in `stride` (kSplitSample on grids of more than
-// 2^20 cells, else every run).  hist[b] takes the work items (per_item points
-// each) of the sampled cells with more than one slab whose cone-size bin is b,
-// hist[kSplitBins] those of every sampled cell.
-constexpr uint32_t kSplitSample = 16;
+// 2^20 cells, else every run; odd, so that the sampled runs take every value
+// of the column bits above the run's 8 index bits, not a fixed subset).
+// hist[b] takes the work items (per_item points each) of the sampled cells
+// with more than one slab whose cone-size bin is b, hist[kSplitBins] those of
+// every sampled cell.  (Counting only the cells that survive Definition 3
+// picked the same cells on the anti-correlated inputs and cost twice as much.)
+constexpr uint32_t kSplitSample = 17;
 
 __global__ __launch_bounds__(kThreads) void k_split_hist(GridDesc gd, const uint32_t *__restrict__ cnt,
                                                          uint32_t per_item, uint32_t stride,
@@ -371,11 +374,11 @@ __global__ __launch_bounds__(kThreads) void k_split_hist(GridDesc gd, const uint
         if (s_hist[b] != 0u) atomicAdd(&hist[b], s_hist[b]);
 }
 
-// One thread: the lowest bin B whose sampled items and above are at most
-// 1 / share of all items (share 0: as many as the item array's estimated room
-// takes), and never more than that room over g - 1 (a split cell's items
-// become at most g times as many); the threshold is the smallest cone-size
-// estimate of bin B (cells at or above it are split, cellops.h).
+// One thread: the highest bin B whose sampled items and above reach 1 / share
+// of all items (share 0: as many as the item array's estimated room takes),
+// and never more than that room over g - 1 (a split cell's items become at
+// most g times as many); the threshold is the smallest cone-size estimate of
+// bin B (cells at or above it are split, cellops.h).
 __global__ void k_split_pick(const uint32_t *__restrict__ hist, uint32_t share, uint32_t n, uint32_t g,
                              uint32_t stride, uint32_t *__restrict__ ctr)
 {
@@ -386,11 +389,11 @@ __global__ void k_split_pick(const uint32_t *__restrict__ hist, uint32_t share, 
     target /= stride;  // in sampled items
     uint64_t acc = 0ull;
     uint32_t b = (uint32_t)kSplitBins;
-    while (b > 1u && acc + hist[b - 1u] <= target) {  // bin 0: cone of one cell
+    while (b > 1u && acc < target) {  // bin 0: cone of one cell
         acc += hist[b - 1u];
         --b;
     }
-    const float thr = b >= (uint32_t)kSplitBins ? __builtin_inff() : exp2f(((float)b - 0.5f) * 0.25f);
+    const float thr = b >= (uint32_t)kSplitBins ? __builtin_inff() : exp2f(((float)b - 0.5f) * 0.125f);
     ctr[kCtrSplitThr] = __float_as_uint(thr);
 }
 
