@@ -374,14 +374,21 @@ __global__ __launch_bounds__(kThreads) void k_split_hist(GridDesc gd, const uint
         if (s_hist[b] != 0u) atomicAdd(&hist[b], s_hist[b]);
 }
 
-// One thread: the highest bin B whose sampled items and above reach 1 / share
+// The highest bin B whose sampled items and above reach 1 / share
 // of all items (share 0: as many as the item array's estimated room takes),
 // and never more than that room over g - 1 (a split cell's items become at
 // most g times as many); the threshold is the smallest cone-size estimate of
 // bin B (cells at or above it are split, cellops.h).
-__global__ void k_split_pick(const uint32_t *__restrict__ hist, uint32_t share, uint32_t n, uint32_t g,
-                             uint32_t stride, uint32_t *__restrict__ ctr)
+__global__ __launch_bounds__(kThreads) void k_split_pick(const uint32_t *__restrict__ hist_g, uint32_t share,
+                                                         uint32_t n, uint32_t g, uint32_t stride,
+                                                         uint32_t *__restrict__ ctr)
 {
+    // the histogram into LDS first: one thread walking it in global memory
+    // waits on one dependent load per bin
+    __shared__ uint32_t hist[kSplitBins + 1];
+    for (int b = threadIdx.x; b <= kSplitBins; b += kThreads) hist[b] = hist_g[b];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const uint64_t total = (uint64_t)hist[kSplitBins] * stride;
     const uint64_t room = total < n ? ((uint64_t)n - total) / (g > 1u ? g - 1u : 1u) : 0ull;
     uint64_t target = share != 0u ? total / share : room;
@@ -424,7 +431,7 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, int64_t n,
         hipLaunchKernelGGL(k_split_hist, dim3(hb), dim3(kThreads), 0, st, gd, (const uint32_t *)ws.cnt,
                            (uint32_t)gd.m, stride, ws.bcur);
         // gd.split 2: as many cells as the item array has room for (tests)
-        hipLaunchKernelGGL(k_split_pick, dim3(1), dim3(1), 0, st, (const uint32_t *)ws.bcur,
+        hipLaunchKernelGGL(k_split_pick, dim3(1), dim3(kThreads), 0, st, (const uint32_t *)ws.bcur,
                            gd.split == 2 ? 0u : split_share(), (uint32_t)n, (uint32_t)gd.g, stride, ws.ctr);
     }
     hipLaunchKernelGGL(k_cell_rec, rgrid, dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
