@@ -20,9 +20,9 @@
 // A passing cell's record (first sorted position and count) is loaded on the
 // turn after its walk record, and its points go into the lane's candidate
 // queue (the current range and one pending range).  The walk steps only while
-// the queue can take what the step may add.  Screening (up to two candidates
-// per lane and turn) and the exact test of one deferred candidate are those
-// of refine_core.h.  (Running them only when many lanes of the wave hold
+// the queue can take what the step may add.  Screening (one candidate per
+// lane and turn) and the exact test of one deferred candidate are those of
+// refine_core.h.  (Running them only when many lanes of the wave hold
 // candidates, so that the wave executes that code less often, was slower:
 // lanes with full queues stop walking until then.)
 #pragma once
@@ -141,9 +141,7 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
             }
         }
         const bool c0ok = active && cur < end;
-        const bool c1ok = active && cur + 1 < end;
         const uint64_t f0 = buffer_u64(rs_fkeys, c0ok ? cur * 8u : kMcNoLoad);
-        const uint64_t f1 = buffer_u64(rs_fkeys, c1ok ? cur * 8u + 8u : kMcNoLoad);
         const bool exok = active && exmask != 0u;
         uint32_t e[D];
         if (exok) load_keys<D>(v.keys, ex, e);
@@ -211,41 +209,35 @@ __device__ void refine_loop_mc(const RefineView &v, const uint64_t *__restrict__
             exmask &= ~tb;
         }
 
-        // ---- screening of up to two candidates (refine_core.h)
+        // ---- screening of one candidate (as in refine_core.h, which takes up
+        // to two per turn: with the walk records a turn's candidate work is
+        // rare, and the second screen cost more issue slots than it saved turns)
         if (c0ok) {
-            uint32_t adv = 0u;
+            const uint32_t self = cur - qstart;
+            const uint32_t act = alive & ~(self < (uint32_t)M ? (1u << self) : 0u);
+            uint32_t le_bits = 0u, lt_bits = 0u;
 #pragma unroll
-            for (int cnd = 0; cnd < 2; ++cnd) {
-                if (cnd == 1 && !c1ok) break;
-                const uint32_t cidx = cur + (uint32_t)cnd;
-                const uint32_t self = cidx - qstart;
-                const uint32_t act = alive & ~(self < (uint32_t)M ? (1u << self) : 0u);
-                uint32_t le_bits = 0u, lt_bits = 0u;
-#pragma unroll
-                for (int t = 0; t < M; ++t) {
-                    const uint64_t diff = qf[t] - (cnd == 0 ? f0 : f1);
-                    const uint64_t nle = ~diff & kHigh;
-                    const uint64_t nlt = ~(diff - kOnes) & kHigh;
-                    le_bits |= nle == 0ull ? (1u << t) : 0u;
-                    lt_bits |= nlt == 0ull ? (1u << t) : 0u;
-                }
-                tests += (uint32_t)__popc(act);
-                alive &= ~(lt_bits & act);
-                uint32_t pass = le_bits & ~lt_bits & act;
-                pass &= alive;
-                if (pass == 0u) {
-                    ++adv;
-                    continue;
-                }
-                if (exmask == 0u) {
-                    ex = cidx;
-                    exmask = pass;
-                    ++adv;
-                    continue;
-                }
-                break;
+            for (int t = 0; t < M; ++t) {
+                const uint64_t diff = qf[t] - f0;
+                const uint64_t nle = ~diff & kHigh;
+                const uint64_t nlt = ~(diff - kOnes) & kHigh;
+                le_bits |= nle == 0ull ? (1u << t) : 0u;
+                lt_bits |= nlt == 0ull ? (1u << t) : 0u;
             }
-            cur += adv;
+            tests += (uint32_t)__popc(act);
+            alive &= ~(lt_bits & act);
+            const uint32_t pass = le_bits & ~lt_bits & act & alive;
+            // a candidate that needs the exact test waits while another holds it
+            bool adv = true;
+            if (pass != 0u) {
+                if (exmask == 0u) {
+                    ex = cur;
+                    exmask = pass;
+                } else {
+                    adv = false;
+                }
+            }
+            if (adv) ++cur;
             if (cur >= end && pcur < pend) {
                 cur = pcur;
                 end = pend;
