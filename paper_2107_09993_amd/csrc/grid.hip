@@ -383,10 +383,18 @@ __global__ __launch_bounds__(kThreads) void k_split_pick(const uint32_t *__restr
                                                          uint32_t n, uint32_t g, uint32_t stride,
                                                          uint32_t *__restrict__ ctr)
 {
-    // the histogram into LDS first: one thread walking it in global memory
-    // waits on one dependent load per bin
+    // the histogram and its sums over chunks of 64 bins into LDS first, so that
+    // the walk down from the top bin takes few dependent reads
+    constexpr int kChunk = 64, kChunks = kSplitBins / kChunk;
     __shared__ uint32_t hist[kSplitBins + 1];
+    __shared__ uint64_t csum[kChunks];
     for (int b = threadIdx.x; b <= kSplitBins; b += kThreads) hist[b] = hist_g[b];
+    __syncthreads();
+    if (threadIdx.x < (unsigned)kChunks) {
+        uint64_t t = 0ull;
+        for (int b = 0; b < kChunk; ++b) t += hist[threadIdx.x * kChunk + b];
+        csum[threadIdx.x] = t;
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
     const uint64_t total = (uint64_t)hist[kSplitBins] * stride;
@@ -394,11 +402,16 @@ __global__ __launch_bounds__(kThreads) void k_split_pick(const uint32_t *__restr
     uint64_t target = share != 0u ? total / share : room;
     if (target > room) target = room;
     target /= stride;  // in sampled items
-    uint64_t acc = 0ull;
+    // B: the highest bin whose sampled items and above reach the target (at
+    // least 1: bin 0 is a cone of one cell); none if the target is 0
     uint32_t b = (uint32_t)kSplitBins;
-    while (b > 1u && acc < target) {  // bin 0: cone of one cell
-        acc += hist[b - 1u];
-        --b;
+    if (target != 0ull) {
+        uint64_t acc = 0ull;
+        int c = kChunks - 1;
+        while (c > 0 && acc + csum[c] < target) acc += csum[c--];
+        int i = c * kChunk + kChunk - 1;
+        while (i > 1 && acc + hist[i] < target) acc += hist[i--];
+        b = (uint32_t)i;
     }
     const float thr = b >= (uint32_t)kSplitBins ? __builtin_inff() : exp2f(((float)b - 0.5f) * 0.125f);
     ctr[kCtrSplitThr] = __float_as_uint(thr);
