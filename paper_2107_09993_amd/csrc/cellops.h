@@ -90,13 +90,17 @@ __host__ __device__ __forceinline__ uint64_t lc_step_word(uint64_t w, uint64_t s
 //   i.e. a non-empty cell has a smaller column in every dimension (Definition 3);
 //   mask bit k    iff  column k of x is >= 1 and lc(x - e_k) = 1, i.e. the cone
 //                      below x - e_k still holds a non-empty cell.
+// D > 0: the dimension count as a compile-time constant (gd.d == D).
+template <int D = 0>
 __device__ __forceinline__ uint64_t cell_record(const GridDesc &gd, const uint32_t *__restrict__ cnt,
                                                 const uint64_t *__restrict__ lcb, uint32_t x,
                                                 bool &occ, bool &surv)
 {
+    const int dd = D > 0 ? D : gd.d;
     uint32_t nbr = 0u, diag = x;
     bool all_pos = true;
-    for (int k = 0; k < gd.d; ++k) {
+#pragma unroll
+    for (int k = 0; k < dd; ++k) {
         const uint32_t m = gd.mask[k];
         if ((x & m) == 0u) {
             all_pos = false;
@@ -176,13 +180,16 @@ __device__ __forceinline__ uint32_t cell_column(uint32_t x, uint32_t m)
 }
 
 // Cone-size estimate of cell x: prod_k (c_k + 1), the number of cells <= x,
-// from the r bit planes of its Morton index.
+// from the r bit planes of its Morton index (D > 0: gd.d as a constant).
+template <int D = 0>
 __device__ __forceinline__ float cone_cells(const GridDesc &gd, uint32_t x)
 {
+    const int dd = D > 0 ? D : gd.d;
     float p = 1.0f;
-    for (int k = 0; k < gd.d; ++k) {
+#pragma unroll
+    for (int k = 0; k < dd; ++k) {
         uint32_t c = 0u;
-        for (int b = 0; b < gd.r; ++b) c |= ((x >> (b * gd.d + k)) & 1u) << b;
+        for (int b = 0; b < gd.r; ++b) c |= ((x >> (b * dd + k)) & 1u) << b;
         p *= (float)(c + 1u);
     }
     return p;

@@ -250,6 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_lc_step(uint64_t *__restrict__ lcb
 // the items it adds are counted (cell_slabs checks that they fit in n).
 constexpr uint32_t kCellRecBlocks = 2048;
 
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32_t *__restrict__ cnt,
                                                        const uint64_t *__restrict__ lc,
                                                        uint64_t *__restrict__ rec,
@@ -266,12 +267,12 @@ __global__ __launch_bounds__(kThreads) void k_cell_rec(GridDesc gd, const uint32
         const uint32_t x = base + threadIdx.x;
         bool occ = false, surv = false;
         uint64_t r = 0ull;
-        if (x < gd.cells) r = cell_record(gd, cnt, lc, x, occ, surv);
+        if (x < gd.cells) r = cell_record<D>(gd, cnt, lc, x, occ, surv);
         if (split != nullptr && surv) {
             const uint32_t items = (cnt[x] + per_item - 1u) / per_item;
             items_all += items;
             const uint32_t c = cell_column(x, top);
-            if (c >= 1u && cone_cells(gd, x) >= thr) {
+            if (c >= 1u && cone_cells<D>(gd, x) >= thr) {
                 r |= (uint64_t)(c + 1u) << 55;
                 extra += (uint64_t)items * c;
             }
@@ -447,8 +448,20 @@ hipError_t launch_cell_prune(const GridDesc &gd, const Workspace &ws, int64_t n,
         hipLaunchKernelGGL(k_split_pick, dim3(1), dim3(kThreads), 0, st, (const uint32_t *)ws.bcur,
                            gd.split == 2 ? 0u : split_share(), (uint32_t)n, (uint32_t)gd.g, stride, ws.ctr);
     }
-    hipLaunchKernelGGL(k_cell_rec, rgrid, dim3(kThreads), 0, st, gd, ws.cnt, ws.lc,
-                       ws.rec, ws.survbits, stats, split ? ws.ctr : nullptr, (uint32_t)gd.m);
+    switch (gd.d) {
+#define SKYCELL_REC_CASE(DD)                                                                                   \
+    case DD:                                                                                                   \
+        hipLaunchKernelGGL(k_cell_rec<DD>, rgrid, dim3(kThreads), 0, st, gd, ws.cnt, ws.lc, ws.rec, ws.survbits, \
+                           stats, split ? ws.ctr : nullptr, (uint32_t)gd.m);                                   \
+        break;
+        SKYCELL_REC_CASE(1) SKYCELL_REC_CASE(2) SKYCELL_REC_CASE(3) SKYCELL_REC_CASE(4)
+        SKYCELL_REC_CASE(5) SKYCELL_REC_CASE(6) SKYCELL_REC_CASE(7) SKYCELL_REC_CASE(8)
+        SKYCELL_REC_CASE(9) SKYCELL_REC_CASE(10) SKYCELL_REC_CASE(11) SKYCELL_REC_CASE(12)
+        SKYCELL_REC_CASE(13) SKYCELL_REC_CASE(14) SKYCELL_REC_CASE(15) SKYCELL_REC_CASE(16)
+#undef SKYCELL_REC_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
