@@ -29,14 +29,17 @@ __device__ __forceinline__ uint32_t column_u16(uint16_t v, uint32_t g, int bits)
     return c > g - 1u ? g - 1u : (uint32_t)c;
 }
 
-// Equation 1 for point i of an SoA block: Morton index of its cell.
-template <typename T>
+// Equation 1 for point i of an SoA block: Morton index of its cell (D > 0:
+// gd.d as a compile-time constant).
+template <typename T, int D = 0>
 __device__ __forceinline__ uint32_t point_cell(const T *__restrict__ pts, uint32_t n, uint32_t i,
                                                const GridDesc &gd, int value_bits, bool &nan)
 {
     const float gf = (float)gd.g;
+    const int dd = D > 0 ? D : gd.d;
     uint32_t cell = 0u;
-    for (int k = 0; k < gd.d; ++k) {
+#pragma unroll
+    for (int k = 0; k < dd; ++k) {
         const T v = pts[(size_t)k * n + i];
         uint32_t c;
         if constexpr (sizeof(T) == 4)

@@ -107,7 +107,7 @@ constexpr int kHotSlots = 128;
 constexpr uint32_t kNoSlot = 0xFFu;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict__ pts, uint32_t n,
                                                             GridDesc gd, int value_bits,
                                                             uint32_t *__restrict__ cell_of,
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict_
         const bool live = i < n;
         uint32_t cell = 0u;
         if (live) {
-            cell = point_cell(pts, n, i, gd, value_bits, nan);
+            cell = point_cell<T, D>(pts, n, i, gd, value_bits, nan);
             cell_of[i] = cell;
         }
         uint64_t pend = __ballot(live);
@@ -184,17 +184,33 @@ __global__ __launch_bounds__(kThreads) void k_quantize_hist(const T *__restrict_
     if (nan) atomicOr(&ctr[kCtrErr], 1u);
 }
 
+template <typename T>
+static hipError_t launch_quantize_hist_t(const T *pts, int64_t n, const GridDesc &gd, int value_bits,
+                                         const Workspace &ws, hipStream_t st)
+{
+    const dim3 grid = grid_for(n, kThreads * kQuantPer);
+    switch (gd.d) {
+#define SKYCELL_QH_CASE(DD)                                                                                     \
+    case DD:                                                                                                    \
+        hipLaunchKernelGGL((k_quantize_hist<T, DD>), grid, dim3(kThreads), 0, st, pts, (uint32_t)n, gd, value_bits, \
+                           ws.cell_of, ws.rank, ws.cnt, ws.ctr);                                                \
+        break;
+        SKYCELL_QH_CASE(1) SKYCELL_QH_CASE(2) SKYCELL_QH_CASE(3) SKYCELL_QH_CASE(4)
+        SKYCELL_QH_CASE(5) SKYCELL_QH_CASE(6) SKYCELL_QH_CASE(7) SKYCELL_QH_CASE(8)
+        SKYCELL_QH_CASE(9) SKYCELL_QH_CASE(10) SKYCELL_QH_CASE(11) SKYCELL_QH_CASE(12)
+        SKYCELL_QH_CASE(13) SKYCELL_QH_CASE(14) SKYCELL_QH_CASE(15) SKYCELL_QH_CASE(16)
+#undef SKYCELL_QH_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_quantize_hist(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                                 int value_bits, const Workspace &ws, hipStream_t st)
 {
-    const dim3 grid = grid_for(n, kThreads * kQuantPer);
-    if (dtype == SKYCELL_DTYPE_F32)
-        hipLaunchKernelGGL(k_quantize_hist<float>, grid, dim3(kThreads), 0, st, (const float *)pts, (uint32_t)n, gd,
-                           value_bits, ws.cell_of, ws.rank, ws.cnt, ws.ctr);
-    else
-        hipLaunchKernelGGL(k_quantize_hist<uint16_t>, grid, dim3(kThreads), 0, st, (const uint16_t *)pts,
-                           (uint32_t)n, gd, value_bits, ws.cell_of, ws.rank, ws.cnt, ws.ctr);
-    return hipGetLastError();
+    if (dtype == SKYCELL_DTYPE_F32) return launch_quantize_hist_t((const float *)pts, n, gd, value_bits, ws, st);
+    return launch_quantize_hist_t((const uint16_t *)pts, n, gd, value_bits, ws, st);
 }
 
 // ------------------------------------------------------------------ K3
