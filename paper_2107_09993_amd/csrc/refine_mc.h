@@ -25,6 +25,11 @@
 // refine_core.h.  (Running them only when many lanes of the wave hold
 // candidates, so that the wave executes that code less often, was slower:
 // lanes with full queues stop walking until then.)
+//
+// A slab item (kItemSlab, cellops.h) walks one slab of its cell's cone: it
+// starts at the slab's corner and never steps along dimension D-1.  Its query
+// points' flags start set, and it clears those of the points it finds
+// dominated; a whole-cone item sets the flags of its surviving points.
 #pragma once
 
 #include "common.h"
