@@ -677,7 +677,24 @@ __global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict_
 
 // Pass 2: the XCD with label x sweeps the x-th eighth of the staged rows in
 // order, kThreads rows per workgroup and step, and writes each row to its
-// sorted position start(cell) + rank.
+// sorted position start(cell) + rank.  Each thread loads its next row right
+// after the current row's cell record, so that row's HBM latency overlaps the
+// record load and the stores (one workgroup per CU keeps the rows in flight
+// on an XCD inside about one bucket's window of sorted positions).
+template <int RW>
+__device__ __forceinline__ void load_stage_row(const uint32_t *__restrict__ stage, uint64_t r, uint32_t (&w)[RW])
+{
+    const uint4 *row = reinterpret_cast<const uint4 *>(stage + (size_t)r * RW);
+#pragma unroll
+    for (int q = 0; q < RW / 4; ++q) {
+        const uint4 v = row[q];
+        w[4 * q] = v.x;
+        w[4 * q + 1] = v.y;
+        w[4 * q + 2] = v.z;
+        w[4 * q + 3] = v.w;
+    }
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_scatter_rows(int value_bits,
                                                            const uint32_t *__restrict__ stage,
@@ -692,23 +709,22 @@ __global__ __launch_bounds__(kThreads) void k_scatter_rows(int value_bits,
     const uint32_t per = gridDim.x / kNumXcd;  // workgroups per XCD
     const uint32_t lo = (uint32_t)(((uint64_t)total * xcd) / kNumXcd);
     const uint32_t hi = (uint32_t)(((uint64_t)total * (xcd + 1)) / kNumXcd);
-    constexpr uint32_t rw = stage_row_words(D);
+    constexpr int rw = (int)stage_row_words(D);
     constexpr int d = D;
     constexpr int fw = fine_words(D);
-    for (uint64_t r = (uint64_t)lo + (uint64_t)(blockIdx.x / kNumXcd) * kThreads + threadIdx.x; r < hi;
-         r += (uint64_t)per * kThreads) {
-        const uint4 *row = reinterpret_cast<const uint4 *>(stage + (size_t)r * rw);
-        uint32_t w[rw];
-#pragma unroll
-        for (uint32_t q = 0; q < rw / 4u; ++q) {
-            const uint4 v = row[q];
-            w[4 * q] = v.x;
-            w[4 * q + 1] = v.y;
-            w[4 * q + 2] = v.z;
-            w[4 * q + 3] = v.w;
-        }
+    const uint64_t step = (uint64_t)per * kThreads;
+    uint64_t r = (uint64_t)lo + (uint64_t)(blockIdx.x / kNumXcd) * kThreads + threadIdx.x;
+    if (r >= hi) return;
+    uint32_t w[rw];
+    load_stage_row<rw>(stage, r, w);
+    for (;;) {
         const uint32_t i = w[d], x = w[d + 1], rk = w[d + 2];
-        const uint32_t pos = rec_start(rec[x]) + rk;
+        const uint64_t cr = rec[x];
+        const uint64_t rn = r + step;
+        const bool more = rn < hi;
+        uint32_t wn[rw];
+        load_stage_row<rw>(stage, more ? rn : r, wn);  // unconditional: no wait for it at a join
+        const uint32_t pos = rec_start(cr) + rk;
         uint32_t *dst = keys + (size_t)pos * d;
         uint64_t *fdst = fkeys + (size_t)pos * fw;
         uint64_t word = 0ull;
@@ -731,6 +747,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter_rows(int value_bits,
             }
         }
         sidx[pos] = (int32_t)i;
+        if (!more) break;
+        r = rn;
+#pragma unroll
+        for (int q = 0; q < rw; ++q) w[q] = wn[q];
     }
 }
 
