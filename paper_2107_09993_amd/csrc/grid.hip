@@ -554,6 +554,29 @@ static inline uint8_t scatter_live_flag(const GridDesc &gd) { return gd.m == kWa
 // their lines are completed in that XCD's L2.
 constexpr int kStagePts = 16;  // points per thread in the counting and staging passes
 
+// The cell, rank and survival word of each of a thread's kStagePts points,
+// loaded in three batches (indices, then survival words) so that the loads of
+// all points are in flight together.  Points past n read as removed, cell 0.
+__device__ __forceinline__ void load_stage_ids(uint32_t n, uint32_t i0, const uint32_t *__restrict__ cell_of,
+                                               const uint32_t *__restrict__ rank,
+                                               const uint64_t *__restrict__ survbits, uint32_t (&cell)[kStagePts],
+                                               uint32_t (&rk)[kStagePts], uint64_t (&sw)[kStagePts])
+{
+#pragma unroll
+    for (int j = 0; j < kStagePts; ++j) {
+        const uint32_t i = i0 + (uint32_t)j * kThreads;
+        cell[j] = i < n ? cell_of[i] : 0u;
+        rk[j] = i < n ? rank[i] : kRankRemoved;
+    }
+#pragma unroll
+    for (int j = 0; j < kStagePts; ++j) sw[j] = survbits[cell[j] >> 6];
+}
+
+__device__ __forceinline__ bool stage_live(uint32_t cell, uint32_t rk, uint64_t sw)
+{
+    return ((sw >> (cell & 63u)) & 1ull) != 0ull && rk != kRankRemoved;
+}
+
 // Pass 1a: per-workgroup bucket counts of the points that survive (their cell
 // survives and the pivot pre-filter kept them), added into lab_cnt[bucket][label].
 __global__ __launch_bounds__(kThreads) void k_scatter_count(uint32_t n, uint32_t nb, uint32_t sh,
@@ -566,15 +589,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter_count(uint32_t n, uint32_t
     for (uint32_t t = threadIdx.x; t < nb; t += kThreads) s_cnt[t] = 0u;
     __syncthreads();
     const uint32_t i0 = blockIdx.x * (uint32_t)(kThreads * kStagePts) + threadIdx.x;
+    uint32_t cell[kStagePts], rk[kStagePts];
+    uint64_t sw[kStagePts];
+    load_stage_ids(n, i0, cell_of, rank, survbits, cell, rk, sw);
 #pragma unroll
-    for (int j = 0; j < kStagePts; ++j) {
-        const uint32_t i = i0 + (uint32_t)j * kThreads;
-        if (i < n) {
-            const uint32_t x = cell_of[i];
-            if (((survbits[x >> 6] >> (x & 63u)) & 1ull) != 0ull && rank[i] != kRankRemoved)
-                atomicAdd(&s_cnt[x >> sh], 1u);
-        }
-    }
+    for (int j = 0; j < kStagePts; ++j)
+        if (stage_live(cell[j], rk[j], sw[j])) atomicAdd(&s_cnt[cell[j] >> sh], 1u);
     __syncthreads();
     const uint32_t lab = blockIdx.x % kNumXcd;
     for (uint32_t t = threadIdx.x; t < nb; t += kThreads)
@@ -619,8 +639,12 @@ __device__ __forceinline__ uint32_t raw_word(uint16_t v) { return (uint32_t)v; }
 // Pass 1c: the same points per workgroup as pass 1a; the LDS atomic gives each
 // point its slot in the workgroup's run of its bucket, one global atomic per
 // (bucket, label) reserves the run.  Clears the output flag of every point.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict__ pts, uint32_t n, int d,
+// Rows are written kStageGroup points at a time, the coordinates of the group
+// loaded before any of its rows is stored.
+constexpr int kStageGroup = 4;
+
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict__ pts, uint32_t n,
                                                             uint32_t nb, uint32_t sh,
                                                             const uint32_t *__restrict__ cell_of,
                                                             const uint32_t *__restrict__ rank,
@@ -634,18 +658,15 @@ __global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict_
     __syncthreads();
     const uint32_t i0 = blockIdx.x * (uint32_t)(kThreads * kStagePts) + threadIdx.x;
     uint32_t cell[kStagePts], rk[kStagePts], slot[kStagePts];
+    {
+        uint64_t sw[kStagePts];
+        load_stage_ids(n, i0, cell_of, rank, survbits, cell, rk, sw);
 #pragma unroll
-    for (int j = 0; j < kStagePts; ++j) {
-        const uint32_t i = i0 + (uint32_t)j * kThreads;
-        slot[j] = ~0u;
-        cell[j] = 0u;
-        rk[j] = 0u;
-        if (i < n) {
-            cell[j] = cell_of[i];
-            rk[j] = rank[i];
-            const bool live = ((survbits[cell[j] >> 6] >> (cell[j] & 63u)) & 1ull) != 0ull && rk[j] != kRankRemoved;
-            flag[i] = live ? live_flag : (uint8_t)0;
-            if (live) slot[j] = atomicAdd(&s_cnt[cell[j] >> sh], 1u);
+        for (int j = 0; j < kStagePts; ++j) {
+            const uint32_t i = i0 + (uint32_t)j * kThreads;
+            const bool live = stage_live(cell[j], rk[j], sw[j]);
+            if (i < n) flag[i] = live ? live_flag : (uint8_t)0;
+            slot[j] = live ? atomicAdd(&s_cnt[cell[j] >> sh], 1u) : ~0u;
         }
     }
     __syncthreads();
@@ -655,22 +676,34 @@ __global__ __launch_bounds__(kThreads) void k_scatter_stage(const T *__restrict_
         s_cnt[t] = c != 0u ? atomicAdd(&lab_cur[t * kNumXcd + lab], c) : 0u;
     }
     __syncthreads();
-    const uint32_t rw = stage_row_words(d);
+    constexpr uint32_t rw = stage_row_words(D);
 #pragma unroll
-    for (int j = 0; j < kStagePts; ++j) {
-        if (slot[j] == ~0u) continue;
-        const uint32_t i = i0 + (uint32_t)j * kThreads;
-        uint4 *row = reinterpret_cast<uint4 *>(stage + (size_t)(s_cnt[cell[j] >> sh] + slot[j]) * rw);
-        // words 0..d-1 coordinates, d index, d+1 cell, d+2 rank, then zero padding
-        for (uint32_t q = 0; q < rw / 4u; ++q) {
-            uint32_t w[4];
+    for (int g0 = 0; g0 < kStagePts; g0 += kStageGroup) {
+        uint32_t c[kStageGroup][D];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = (int)(4u * q) + e;
-                w[e] = k < d ? raw_word(pts[(size_t)k * n + i])
-                             : k == d ? i : k == d + 1 ? cell[j] : k == d + 2 ? rk[j] : 0u;
+        for (int t = 0; t < kStageGroup; ++t) {
+            const int j = g0 + t;
+            const uint32_t i = i0 + (uint32_t)j * kThreads;
+#pragma unroll
+            for (int k = 0; k < D; ++k) c[t][k] = slot[j] != ~0u ? raw_word(pts[(size_t)k * n + i]) : 0u;
+        }
+#pragma unroll
+        for (int t = 0; t < kStageGroup; ++t) {
+            const int j = g0 + t;
+            if (slot[j] == ~0u) continue;
+            const uint32_t i = i0 + (uint32_t)j * kThreads;
+            uint4 *row = reinterpret_cast<uint4 *>(stage + (size_t)(s_cnt[cell[j] >> sh] + slot[j]) * rw);
+            // words 0..D-1 coordinates, D index, D+1 cell, D+2 rank, then zero padding
+#pragma unroll
+            for (uint32_t q = 0; q < rw / 4u; ++q) {
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = (int)(4u * q) + e;
+                    w[e] = k < D ? c[t][k < D ? k : 0] : k == D ? i : k == D + 1 ? cell[j] : k == D + 2 ? rk[j] : 0u;
+                }
+                row[q] = make_uint4(w[0], w[1], w[2], w[3]);
             }
-            row[q] = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
 }
@@ -780,9 +813,21 @@ static hipError_t launch_scatter_two_pass(const T *pts, int64_t n, const GridDes
                        (const uint32_t *)ws.cell_of, (const uint32_t *)ws.rank, (const uint64_t *)ws.survbits,
                        ws.bcur);
     hipLaunchKernelGGL(k_scatter_bases, dim3(1), dim3(kThreads), 0, st, ws.bcur, labs);
-    hipLaunchKernelGGL(k_scatter_stage<T>, pgrid, dim3(kThreads), 0, st, pts, (uint32_t)n, gd.d, nb, sh,
-                       (const uint32_t *)ws.cell_of, (const uint32_t *)ws.rank, (const uint64_t *)ws.survbits,
-                       ws.bcur, ws.stage, ws.flag, scatter_live_flag(gd));
+    switch (gd.d) {
+#define SKYCELL_STAGE_CASE(DD)                                                                                   \
+    case DD:                                                                                                     \
+        hipLaunchKernelGGL((k_scatter_stage<T, DD>), pgrid, dim3(kThreads), 0, st, pts, (uint32_t)n, nb, sh,     \
+                           (const uint32_t *)ws.cell_of, (const uint32_t *)ws.rank,                               \
+                           (const uint64_t *)ws.survbits, ws.bcur, ws.stage, ws.flag, scatter_live_flag(gd));     \
+        break;
+        SKYCELL_STAGE_CASE(1) SKYCELL_STAGE_CASE(2) SKYCELL_STAGE_CASE(3) SKYCELL_STAGE_CASE(4)
+        SKYCELL_STAGE_CASE(5) SKYCELL_STAGE_CASE(6) SKYCELL_STAGE_CASE(7) SKYCELL_STAGE_CASE(8)
+        SKYCELL_STAGE_CASE(9) SKYCELL_STAGE_CASE(10) SKYCELL_STAGE_CASE(11) SKYCELL_STAGE_CASE(12)
+        SKYCELL_STAGE_CASE(13) SKYCELL_STAGE_CASE(14) SKYCELL_STAGE_CASE(15) SKYCELL_STAGE_CASE(16)
+#undef SKYCELL_STAGE_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
     const unsigned blocks = (unsigned)(((num_cus * scatter_row_blocks() + kNumXcd - 1) / kNumXcd) * kNumXcd);
     switch (gd.d) {
 #define SKYCELL_ROWS_CASE(DD)                                                                                    \
