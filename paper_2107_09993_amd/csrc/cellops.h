@@ -120,31 +120,33 @@ __device__ __forceinline__ uint64_t cell_record(const GridDesc &gd, const uint32
 }
 
 // Scatter of point i of a surviving cell to sorted position pos: exact
-// order-preserving keys and packed screening columns.
-template <typename T>
-__device__ __forceinline__ void scatter_point(const T *__restrict__ pts, uint32_t n, int d,
-                                              int value_bits, uint32_t i, uint32_t pos,
-                                              uint32_t *__restrict__ keys,
-                                              uint64_t *__restrict__ fkeys,
-                                              int32_t *__restrict__ sidx)
+// order-preserving keys and packed screening columns.  The D coordinates are
+// loaded before the first store, so their loads are in flight together.
+template <typename T, int D>
+__device__ __forceinline__ void scatter_point(const T *__restrict__ pts, uint32_t n, int value_bits, uint32_t i,
+                                              uint32_t pos, uint32_t *__restrict__ keys,
+                                              uint64_t *__restrict__ fkeys, int32_t *__restrict__ sidx)
 {
-    uint32_t *dst = keys + (size_t)pos * d;
-    const int fw = fine_words(d);
+    T v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = pts[(size_t)k * n + i];
+    uint32_t *dst = keys + (size_t)pos * D;
+    constexpr int fw = fine_words(D);
     uint64_t *fdst = fkeys + (size_t)pos * fw;
     uint64_t word = 0ull;
     bool nan = false;
-    for (int k = 0; k < d; ++k) {
-        const T v = pts[(size_t)k * n + i];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
         uint32_t f;
         if constexpr (sizeof(T) == 4) {
-            dst[k] = f32_key(v);
-            f = column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan);
+            dst[k] = f32_key(v[k]);
+            f = column_f32(v[k], (float)kFineCols, (uint32_t)kFineCols, nan);
         } else {
-            dst[k] = (uint32_t)v;
-            f = column_u16(v, (uint32_t)kFineCols, value_bits);
+            dst[k] = (uint32_t)v[k];
+            f = column_u16(v[k], (uint32_t)kFineCols, value_bits);
         }
         word |= (uint64_t)f << (8 * (k & 7));
-        if ((k & 7) == 7 || k == d - 1) {
+        if ((k & 7) == 7 || k == D - 1) {
             fdst[k >> 3] = word;
             word = 0ull;
         }

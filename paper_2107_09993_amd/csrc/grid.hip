@@ -518,9 +518,8 @@ hipError_t launch_cell_scan(const GridDesc &gd, const Workspace &ws, int64_t n, 
 // order inside a cell follows the histogram's (arbitrary) order; the skyline
 // does not depend on it.  Writes the exact keys and the packed screening
 // columns, and clears the output flag of every point.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts, uint32_t n, int d,
-                                                      int value_bits,
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts, uint32_t n, int value_bits,
                                                       const uint32_t *__restrict__ cell_of,
                                                       const uint32_t *__restrict__ rank,
                                                       const uint64_t *__restrict__ rec,
@@ -533,12 +532,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const T *__restrict__ pts,
     if (i >= n) return;
     flag[i] = 0;
     const uint32_t x = cell_of[i];
+    const uint32_t rk = rank[i];  // loaded with the cell, not behind its record
     const uint64_t r = rec[x];
-    if (!rec_surv(r)) return;
-    const uint32_t rk = rank[i];
-    if (rk == kRankRemoved) return;
+    if (!rec_surv(r) || rk == kRankRemoved) return;
     if (live_flag) flag[i] = live_flag;
-    scatter_point(pts, n, d, value_bits, i, rec_start(r) + rk, keys, fkeys, sidx);
+    scatter_point<T, D>(pts, n, value_bits, i, rec_start(r) + rk, keys, fkeys, sidx);
 }
 
 // Output flag the scatter gives each surviving point: the lane form of the
@@ -847,6 +845,28 @@ static hipError_t launch_scatter_two_pass(const T *pts, int64_t n, const GridDes
     return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t launch_scatter_one_pass(const T *pts, int64_t n, const GridDesc &gd, const Workspace &ws,
+                                          int value_bits, hipStream_t st)
+{
+    switch (gd.d) {
+#define SKYCELL_ONE_PASS_CASE(DD)                                                                                \
+    case DD:                                                                                                     \
+        hipLaunchKernelGGL((k_scatter<T, DD>), grid_for(n), dim3(kThreads), 0, st, pts, (uint32_t)n, value_bits, \
+                           ws.cell_of, ws.rank, ws.rec, ws.keys, ws.fkeys, ws.sidx, ws.flag,                      \
+                           scatter_live_flag(gd));                                                               \
+        break;
+        SKYCELL_ONE_PASS_CASE(1) SKYCELL_ONE_PASS_CASE(2) SKYCELL_ONE_PASS_CASE(3) SKYCELL_ONE_PASS_CASE(4)
+        SKYCELL_ONE_PASS_CASE(5) SKYCELL_ONE_PASS_CASE(6) SKYCELL_ONE_PASS_CASE(7) SKYCELL_ONE_PASS_CASE(8)
+        SKYCELL_ONE_PASS_CASE(9) SKYCELL_ONE_PASS_CASE(10) SKYCELL_ONE_PASS_CASE(11) SKYCELL_ONE_PASS_CASE(12)
+        SKYCELL_ONE_PASS_CASE(13) SKYCELL_ONE_PASS_CASE(14) SKYCELL_ONE_PASS_CASE(15) SKYCELL_ONE_PASS_CASE(16)
+#undef SKYCELL_ONE_PASS_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 static hipError_t launch_scatter_points(const void *pts, int dtype, int64_t n, const GridDesc &gd,
                                         const Workspace &ws, int value_bits, int num_cus, hipStream_t st)
 {
@@ -856,14 +876,8 @@ static hipError_t launch_scatter_points(const void *pts, int dtype, int64_t n, c
         return launch_scatter_two_pass<uint16_t>((const uint16_t *)pts, n, gd, ws, value_bits, num_cus, st);
     }
     if (dtype == SKYCELL_DTYPE_F32)
-        hipLaunchKernelGGL(k_scatter<float>, grid_for(n), dim3(kThreads), 0, st, (const float *)pts,
-                           (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank, ws.rec, ws.keys, ws.fkeys,
-                           ws.sidx, ws.flag, scatter_live_flag(gd));
-    else
-        hipLaunchKernelGGL(k_scatter<uint16_t>, grid_for(n), dim3(kThreads), 0, st,
-                           (const uint16_t *)pts, (uint32_t)n, gd.d, value_bits, ws.cell_of, ws.rank,
-                           ws.rec, ws.keys, ws.fkeys, ws.sidx, ws.flag, scatter_live_flag(gd));
-    return hipGetLastError();
+        return launch_scatter_one_pass<float>((const float *)pts, n, gd, ws, value_bits, st);
+    return launch_scatter_one_pass<uint16_t>((const uint16_t *)pts, n, gd, ws, value_bits, st);
 }
 
 hipError_t launch_scatter(const void *pts, int dtype, int64_t n, const GridDesc &gd,
