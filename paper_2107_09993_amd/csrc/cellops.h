@@ -119,6 +119,26 @@ __device__ __forceinline__ uint64_t cell_record(const GridDesc &gd, const uint32
     return ((uint64_t)(surv ? 1u : 0u) << 63) | ((uint64_t)nbr << 47) | (cs << 32);
 }
 
+// One point's D key words stored at dst = keys + pos * D (the key array is
+// 256-byte aligned), with 16- or 8-byte stores where D makes every row aligned
+// to them: fewer, wider scattered stores than one per word.
+template <int D>
+__device__ __forceinline__ void store_key_row(uint32_t *__restrict__ dst, const uint32_t (&kw)[D])
+{
+    if constexpr (D % 4 == 0) {
+        uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+        for (int q = 0; q < D / 4; ++q) d4[q] = make_uint4(kw[4 * q], kw[4 * q + 1], kw[4 * q + 2], kw[4 * q + 3]);
+    } else if constexpr (D % 2 == 0) {
+        uint2 *d2 = reinterpret_cast<uint2 *>(dst);
+#pragma unroll
+        for (int q = 0; q < D / 2; ++q) d2[q] = make_uint2(kw[2 * q], kw[2 * q + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) dst[k] = kw[k];
+    }
+}
+
 // Scatter of point i of a surviving cell to sorted position pos: exact
 // order-preserving keys and packed screening columns.  The D coordinates are
 // loaded before the first store, so their loads are in flight together.
@@ -135,14 +155,15 @@ __device__ __forceinline__ void scatter_point(const T *__restrict__ pts, uint32_
     uint64_t *fdst = fkeys + (size_t)pos * fw;
     uint64_t word = 0ull;
     bool nan = false;
+    uint32_t kw[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         uint32_t f;
         if constexpr (sizeof(T) == 4) {
-            dst[k] = f32_key(v[k]);
+            kw[k] = f32_key(v[k]);
             f = column_f32(v[k], (float)kFineCols, (uint32_t)kFineCols, nan);
         } else {
-            dst[k] = (uint32_t)v[k];
+            kw[k] = (uint32_t)v[k];
             f = column_u16(v[k], (uint32_t)kFineCols, value_bits);
         }
         word |= (uint64_t)f << (8 * (k & 7));
@@ -151,6 +172,7 @@ __device__ __forceinline__ void scatter_point(const T *__restrict__ pts, uint32_
             word = 0ull;
         }
     }
+    store_key_row<D>(dst, kw);
     sidx[pos] = (int32_t)i;
 }
 

@@ -760,15 +760,16 @@ __global__ __launch_bounds__(kThreads) void k_scatter_rows(int value_bits,
         uint64_t *fdst = fkeys + (size_t)pos * fw;
         uint64_t word = 0ull;
         bool nan = false;
+        uint32_t kw[D];
 #pragma unroll
         for (int k = 0; k < d; ++k) {
             uint32_t f;
             if constexpr (sizeof(T) == 4) {
                 const float v = __uint_as_float(w[k]);
-                dst[k] = f32_key(v);
+                kw[k] = f32_key(v);
                 f = column_f32(v, (float)kFineCols, (uint32_t)kFineCols, nan);
             } else {
-                dst[k] = w[k];
+                kw[k] = w[k];
                 f = column_u16((uint16_t)w[k], (uint32_t)kFineCols, value_bits);
             }
             word |= (uint64_t)f << (8 * (k & 7));
@@ -777,6 +778,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter_rows(int value_bits,
                 word = 0ull;
             }
         }
+        store_key_row<D>(dst, kw);
         sidx[pos] = (int32_t)i;
         if (!more) break;
         r = rn;
